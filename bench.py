@@ -1,0 +1,160 @@
+"""Throughput benchmark: exact frag + defrag round trip of one 4096x4096 RGB
+image (k = 5: DC + 5 AC private as int16 under AES-128-CTR, 58 FP32 public
+coefficients per 8x8 block) on one MI355X.
+
+Prints ONE JSON line (rank 0).  A step is one frag_image + defrag_image of one
+image whose input already sits in HBM; steps rotate over several disjoint
+buffer sets so that no step reads what the previous one left in the caches.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+H, W, C, K_PRIV = 4096, 4096, 3, 5
+
+
+def algorithmic_bytes(H, W, C, npriv, pub_elt=4):
+    """Bytes a frag (or a defrag) must move: the image once, the fragments once."""
+    n = H * W * C
+    nb = n // 64
+    return n + nb * (64 - npriv) * pub_elt + nb * npriv * 2
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """Time the plain FP64 oracle (as it stands) on the host cores, on a bounded
+    sample of the same workload: full-width 4096-pixel strips of the RGB image,
+    frag + defrag, until about budget_s seconds of work are done."""
+    import numpy as np
+
+    import oracle
+    import synth
+    threads = os.cpu_count() or 1
+    oracle.set_threads(threads)
+    mask = (1 << (K_PRIV + 1)) - 1
+    key, ctr0 = synth.aes_key(2), synth.ctr0(2, 0)
+    rows = 256  # one sample unit: 256 x 4096 x 3 samples
+    x = synth.image(rows, W, C, 2, 1).numpy()
+    done_px, spent = 0, 0.0
+    while spent < budget_s:
+        t0 = time.perf_counter()
+        f = oracle.frag(x, mask, key, ctr0)
+        y = oracle.defrag(x.shape, mask, f["public"], key=key, ctr0=ctr0, cipher=f["cipher"],
+                          exc_index=f["exc_index"], exc_value=f["exc_value"])
+        spent += time.perf_counter() - t0
+        assert np.array_equal(y, x)
+        done_px += rows * W
+        if spent > 0 and done_px >= H * W:
+            break
+    return {"value": round(done_px / spent / 1e6, 3), "unit": "MP/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": "%d rows x %d px x %d channels of the 4096x4096 RGB workload (%d MP), frag+defrag, "
+                      "FP64 direct-sum DCT, integer quantiser, scalar AES-CTR" % (done_px // W, W, C, done_px // 10**6)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--sets", type=int, default=4, help="disjoint buffer sets rotated across steps")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1512_02951_amd as sf
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mask = sf.prefix_mask(K_PRIV)
+    key = synth.aes_key(2)
+    sets = []
+    for s in range(args.sets):
+        x = synth.image(H, W, C, 2, s, device=dev)
+        fr = sf.frag_image(x, mask, key, synth.ctr0(2, s))
+        y = torch.empty_like(x)
+        sets.append((x, fr, y, synth.ctr0(2, s)))
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step(i, ev=None):
+        x, fr, y, c0 = sets[i % len(sets)]
+        if ev is not None:
+            ev[0].record()
+        sf.frag_image(x, mask, key, c0, out=fr, status=status)
+        if ev is not None:
+            ev[1].record()
+        sf.defrag_image(fr, key, c0, out=y, status=status)
+        if ev is not None:
+            ev[2].record()
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(args.steps):
+        step(i, evs[i])
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    frag_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    defrag_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    assert int(status.item()) == 0, "device status %d" % status.item()
+    for x, fr, y, _ in sets:
+        assert torch.equal(x, y), "round trip not exact"
+
+    ms = total_ms / args.steps
+    mp = H * W / 1e6
+    per_launch = algorithmic_bytes(H, W, C, K_PRIV + 1)
+    dom_ms, dom = (frag_ms, "frag") if frag_ms >= defrag_ms else (defrag_ms, "defrag")
+    achieved = per_launch / (dom_ms * 1e-3) / 1e9
+    round_trip_gbs = 2 * per_launch / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "MP/s exact frag+defrag round trip (4096^2 RGB)",
+        "value": round(mp / (ms * 1e-3), 1),
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4096x4096 RGB planar uint8, DC+5 AC private (int16, AES-128-CTR), 58 FP32 public "
+                               "coefficients per 8x8 block, bit-exact round trip", "images_per_step": 1,
+                   "buffer_sets": len(sets)},
+        "round_trip_GBps": round(round_trip_gbs, 1),
+        "hbm_frac_round_trip": round(round_trip_gbs / HBM_PEAK_GBS, 4),
+        "frag_ms": round(frag_ms, 5),
+        "defrag_ms": round(defrag_ms, 5),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * sefrag.h -- C ABI of the MI355X (gfx950) selective-fragmentation library.
+ *
+ * Method: the "first level of protection" of the report "Data Protection:
+ * Combining Fragmentation, Encryption, and Dispersion" (Memmi, Kapusta,
+ * Lambein, Qiu), Sec. 6.3.1 and Fig. 6: every 8x8 block of an 8-bit image is
+ * transformed with the orthonormal DCT-II (Sec. 6.1, 6.4.2); a selected set of
+ * low-frequency coefficients (by default DC and the first five zigzag AC
+ * coefficients [0,0],[0,1],[1,0],[2,0],[1,1],[0,2]; the ratio is user-tunable,
+ * Sec. 6.2.1/6.3.1) is stored as integers (Sec. 6.4.3 "11-bit storage", held in
+ * int16) and encrypted with AES-128 (here in counter mode); the remaining
+ * coefficients form the public fragment.  Defragmentation (Sec. 5.2, Fig. 3)
+ * decrypts, merges, inverse-transforms and restores every sample exactly.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* are DEVICE pointers, allocated and owned by the caller;
+ *   all other pointers are host pointers read during the call only.
+ * - Alignment: pixel buffers 8 bytes, fragment and residual buffers 16 bytes
+ *   (torch and hipMalloc allocations satisfy both); otherwise SF_EINVAL.
+ * - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *   default stream).  Host-side validation is synchronous: a negative return
+ *   code means nothing was enqueued.
+ * - The library allocates no memory per call.  On first use of a device it
+ *   uploads small constant tables (AES T-tables, integer DCT basis) and keeps
+ *   them until the process ends.
+ * - Errors: SF_* codes below; sf_last_error() returns a thread-local message
+ *   for the last failing call on this thread.
+ * - Device-detected conditions are OR-ed into *d_status (one uint32 the caller
+ *   zeroes when it wants a fresh reading and reads after synchronising).
+ *
+ * Image and fragment layouts
+ * --------------------------
+ * Image: uint8 planar [channels][height][width], row-major; height and width
+ * are positive multiples of 8 (otherwise SF_ESHAPE); channels >= 1; the
+ * total sample count must stay below 2^32.  Blocks are numbered
+ * b = (c*By + by)*Bx + bx with By = height/8, Bx = width/8.
+ *
+ * Coefficient selection: bit z of private_mask marks zigzag position z (JPEG
+ * order over [u=row frequency, v=column frequency]) as private.  DC plus the
+ * first k AC coefficients is private_mask = (1 << (k+1)) - 1.
+ *
+ * Fragments use the 64-block tile-interleaved layout: tile t covers blocks
+ * 64t .. 64t+n_t-1 with n_t = min(64, nb - 64t); value j (0 <= j < P) of block
+ * 64t+i is element 64*t*P + j*n_t + i.  Values within a block are in zigzag
+ * order (private: the P = popcount(mask) private positions; public: the other
+ * 64 - P positions).
+ *   public fragment : float32 (SF_FP32) or fp16 / bf16 (SF_FP16 / SF_BF16)
+ *                     DCT coefficients.
+ *   private fragment: int16 little-endian integers q = round_half_even(
+ *                     sum_p x_p * round_half_even(2^20 B[n][p]) / 2^20 ),
+ *                     as one byte stream, AES-128-CTR encrypted with counter
+ *                     blocks ctr0 + i (128-bit big-endian increment, NIST
+ *                     SP 800-38A) when an sf_aes_ctr is given.
+ */
+#ifndef SEFRAG_H
+#define SEFRAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define SF_OK 0
+#define SF_EINVAL (-1)    /* null pointer, unknown enum, empty private mask          */
+#define SF_ESHAPE (-2)    /* height/width not positive multiples of 8, or too large  */
+#define SF_ERANGE (-3)    /* a size or capacity argument out of range                */
+#define SF_EHIP (-5)      /* HIP runtime error; see sf_last_error()                  */
+#define SF_ENOTSUP (-6)   /* no gfx950 device, or an unsupported combination         */
+
+/* ---- bits OR-ed into *d_status by the kernels ---- */
+#define SF_STATUS_EXC_OVERFLOW 0x1u  /* more exceptions than capacity; *d_count holds the number found */
+#define SF_STATUS_RESIDUAL_RANGE 0x2u /* a residual fell outside int8 (never for valid fragments)      */
+#define SF_STATUS_PRIVATE_RANGE 0x4u  /* a private integer fell outside int16 (never for uint8 input)  */
+
+/* ---- precisions of the transform and of the public fragment ---- */
+#define SF_FP32 0u  /* plain form: FP32 vector DCT, sparse exception list        */
+#define SF_FP16 1u  /* reduced precision: fp16 MFMA DCT, dense int8 residual plane */
+#define SF_BF16 2u  /* reduced precision: bf16 MFMA DCT (hi/lo basis), residual     */
+
+typedef struct sf_desc {
+  uint32_t height;        /* rows per channel, multiple of 8                         */
+  uint32_t width;         /* columns, multiple of 8                                  */
+  uint32_t channels;      /* planar channels (1 = gray, 3 = RGB)                     */
+  uint32_t precision;     /* SF_FP32, SF_FP16 or SF_BF16                             */
+  uint64_t private_mask;  /* bit z set: zigzag position z is private; must be nonzero */
+} sf_desc;
+
+/* AES-128 key and the 16-byte initial counter block (host memory, copied by
+ * value during the call).  The key schedule is expanded on the host. */
+typedef struct sf_aes_ctr {
+  uint8_t key[16];
+  uint8_t ctr0[16];
+} sf_aes_ctr;
+
+/* Exception list of the plain (SF_FP32) form: samples whose reconstruction
+ * from the stored fragments would not round back to the input.  Written by
+ * frag_image (which sets *d_count), read by defrag_image.  Contents beyond the
+ * count, and the order of entries, are unspecified. */
+typedef struct sf_exceptions {
+  uint32_t *d_count;  /* device, 1 word: number of exceptions found              */
+  uint32_t *d_index;  /* device, capacity words: sample index c*H*W + y*W + x    */
+  uint8_t *d_value;   /* device, capacity bytes: the sample's value              */
+  uint32_t capacity;  /* entries available in d_index / d_value                  */
+} sf_exceptions;
+
+/* Library version string. */
+const char *sf_version(void);
+/* Message for a return code. */
+const char *sf_strerror(int code);
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *sf_last_error(void);
+
+/* Byte sizes of the fragments for a descriptor (host only, no GPU needed).
+ * Any output pointer may be NULL.  residual_bytes is 0 for SF_FP32 and
+ * channels*height*width for the reduced-precision forms.
+ * Returns SF_OK, SF_EINVAL or SF_ESHAPE. */
+int sf_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private_bytes, size_t *residual_bytes);
+
+/* Initialise the library on the current HIP device (optional; every entry
+ * point does it lazily).  Returns SF_OK, SF_ENOTSUP or SF_EHIP. */
+int sf_init(void);
+
+/* frag_image -- fragmentation (Sec. 6.3.1, Fig. 6: DCT 8x8, selection,
+ * AES on the private part, public part left plain; Sec. 6.5.2: all steps on
+ * the GPU).
+ *   d_pixels  : input image, C*H*W bytes.
+ *   d_public  : out, public fragment (size from sf_fragment_sizes).
+ *   d_private : out, private fragment, encrypted when aes != NULL.
+ *   exc       : SF_FP32 only: exception list (may not be NULL for SF_FP32).
+ *   d_residual: SF_FP16/SF_BF16 only: out, int8 plane [C][H][W] with
+ *               x - clamp(round(reconstruction)) (NULL for SF_FP32).
+ *   aes       : key + initial counter, or NULL to leave the private integers
+ *               in clear.
+ *   d_status  : device word for SF_STATUS_* bits (may be NULL).
+ * Output buffers must not overlap the input. */
+int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uint8_t *d_private,
+               const sf_exceptions *exc, int8_t *d_residual, const sf_aes_ctr *aes, uint32_t *d_status,
+               void *stream);
+
+/* defrag_image -- defragmentation (Sec. 5.2, Fig. 3): decrypt the private
+ * fragment, merge with the public coefficients in zigzag order, inverse DCT,
+ * round half to even, clamp to [0,255], then apply the exception list
+ * (SF_FP32) or add the residual plane (SF_FP16/SF_BF16).  Restores the input
+ * of the matching frag_image call bit for bit.  Arguments mirror frag_image;
+ * d_pixels is the output. */
+int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_private, const sf_exceptions *exc,
+                 const int8_t *d_residual, const sf_aes_ctr *aes, uint8_t *d_pixels, uint32_t *d_status,
+                 void *stream);
+
+/* encrypt_private -- AES-128 in counter mode over an arbitrary device buffer
+ * (Sec. 6.2.2/6.5.2: AES on the selected part; SP 800-38A counter mode):
+ *   out[j] = in[j] XOR E_K(ctr0 + first_block + j/16)[j mod 16].
+ * Encryption and decryption are the same call; d_in == d_out is allowed. */
+int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *d_in, uint8_t *d_out,
+                    size_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEFRAG_H */

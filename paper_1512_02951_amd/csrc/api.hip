@@ -1,0 +1,208 @@
+// C ABI entry points: validation, lazy per-device initialisation, dispatch.
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "sf_internal.h"
+
+namespace sf {
+
+static thread_local std::string t_last_error;
+
+int fail(int code, const std::string &msg) {
+  t_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  t_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return SF_EHIP;
+}
+
+int make_geom(const sf_desc *d, Geom *g) {
+  if (!d) return fail(SF_EINVAL, "desc is NULL");
+  if (d->height == 0 || d->width == 0 || d->height % 8 || d->width % 8)
+    return fail(SF_ESHAPE, "height and width must be positive multiples of 8");
+  if (d->channels == 0) return fail(SF_ESHAPE, "channels must be >= 1");
+  const uint64_t samples = (uint64_t)d->height * d->width * d->channels;
+  if (samples >= (1ull << 32)) return fail(SF_ESHAPE, "image must hold fewer than 2^32 samples");
+  if (d->precision > SF_BF16) return fail(SF_EINVAL, "unknown precision");
+  if (d->private_mask == 0) return fail(SF_EINVAL, "private_mask must select at least one coefficient");
+  g->H = d->height;
+  g->W = d->width;
+  g->C = d->channels;
+  g->Bx = d->width / 8;
+  g->By = d->height / 8;
+  g->nb = samples / 64;
+  g->ntiles = (uint32_t)((g->nb + 63) / 64);
+  g->mask = d->private_mask;
+  g->npriv = (uint32_t)__builtin_popcountll(d->private_mask);
+  g->npub = 64 - g->npriv;
+  g->precision = d->precision;
+  return SF_OK;
+}
+
+// Kernels read 8-byte pixel rows and 16-byte private chunks.
+static int check_alignment(const void *pix, const void *pub, const void *priv) {
+  if ((uintptr_t)pix & 7u) return fail(SF_EINVAL, "pixel buffer must be 8-byte aligned");
+  if ((uintptr_t)pub & 15u) return fail(SF_EINVAL, "public fragment must be 16-byte aligned");
+  if ((uintptr_t)priv & 15u) return fail(SF_EINVAL, "private fragment must be 16-byte aligned");
+  return SF_OK;
+}
+
+void make_aes_args(const sf_aes_ctr *aes, AesArgs *a) {
+  memset(a, 0, sizeof(*a));
+  if (!aes) return;
+  a->enabled = 1;
+  aes_expand_key(aes->key, a->key.rk);
+  uint64_t hi = 0, lo = 0;
+  for (int i = 0; i < 8; ++i) hi = (hi << 8) | aes->ctr0[i];
+  for (int i = 8; i < 16; ++i) lo = (lo << 8) | aes->ctr0[i];
+  a->ctr_hi = hi;
+  a->ctr_lo = lo;
+}
+
+static std::mutex g_dev_mu;
+static DeviceState g_dev[64];
+
+int device_state(DeviceState **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(SF_ENOTSUP, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DeviceState &s = g_dev[dev];
+  if (s.device < 0) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(SF_ENOTSUP, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+    const HostTables &t = host_tables();
+    uint32_t *d_t0 = nullptr, *d_q2 = nullptr;
+    if ((e = hipMalloc(&d_t0, sizeof(t.aes_t0))) != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
+    if ((e = hipMalloc(&d_q2, sizeof(t.q2))) != hipSuccess) {
+      (void)hipFree(d_t0);
+      return hip_fail(e, "hipMalloc(tables)");
+    }
+    if ((e = hipMemcpy(d_t0, t.aes_t0, sizeof(t.aes_t0), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_q2, t.q2, sizeof(t.q2), hipMemcpyHostToDevice)) != hipSuccess) {
+      (void)hipFree(d_t0);
+      (void)hipFree(d_q2);
+      return hip_fail(e, "hipMemcpy(tables)");
+    }
+    s.num_cu = prop.multiProcessorCount;
+    s.d_aes_t0 = d_t0;
+    s.d_q2 = d_q2;
+    s.device = dev;
+  }
+  *out = &s;
+  return SF_OK;
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" {
+
+const char *sf_version(void) { return "sefrag 0.1 (gfx950)"; }
+
+const char *sf_strerror(int code) {
+  switch (code) {
+    case SF_OK: return "ok";
+    case SF_EINVAL: return "invalid argument";
+    case SF_ESHAPE: return "invalid image shape";
+    case SF_ERANGE: return "size or capacity out of range";
+    case SF_EHIP: return "HIP runtime error";
+    case SF_ENOTSUP: return "not supported";
+    default: return "unknown error";
+  }
+}
+
+const char *sf_last_error(void) { return t_last_error.c_str(); }
+
+int sf_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private_bytes, size_t *residual_bytes) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  const size_t elt = g.precision == SF_FP32 ? 4 : 2;
+  if (public_bytes) *public_bytes = (size_t)g.nb * g.npub * elt;
+  if (private_bytes) *private_bytes = (size_t)g.nb * g.npriv * 2;
+  if (residual_bytes) *residual_bytes = g.precision == SF_FP32 ? 0 : (size_t)g.nb * 64;
+  t_last_error.clear();
+  return SF_OK;
+}
+
+int sf_init(void) {
+  DeviceState *ds;
+  return device_state(&ds);
+}
+
+int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uint8_t *d_private,
+               const sf_exceptions *exc, int8_t *d_residual, const sf_aes_ctr *aes, uint32_t *d_status,
+               void *stream) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  if (!d_pixels || !d_private || (g.npub && !d_public)) return fail(SF_EINVAL, "NULL fragment or image pointer");
+  if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
+  if (g.precision == SF_FP32) {
+    if (!exc || !exc->d_count || (exc->capacity && (!exc->d_index || !exc->d_value)))
+      return fail(SF_EINVAL, "SF_FP32 needs an exception list");
+  } else {
+    return fail(SF_ENOTSUP, "reduced-precision form not built in this library version");
+  }
+  (void)d_residual;
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  AesArgs a;
+  make_aes_args(aes, &a);
+  rc = launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, *exc, a, d_status, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_private, const sf_exceptions *exc,
+                 const int8_t *d_residual, const sf_aes_ctr *aes, uint8_t *d_pixels, uint32_t *d_status,
+                 void *stream) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  if (!d_pixels || !d_private || (g.npub && !d_public)) return fail(SF_EINVAL, "NULL fragment or image pointer");
+  if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
+  if (g.precision == SF_FP32) {
+    if (!exc || !exc->d_count || (exc->capacity && (!exc->d_index || !exc->d_value)))
+      return fail(SF_EINVAL, "SF_FP32 needs an exception list");
+  } else {
+    return fail(SF_ENOTSUP, "reduced-precision form not built in this library version");
+  }
+  (void)d_residual;
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  AesArgs a;
+  make_aes_args(aes, &a);
+  rc = launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, *exc, a, d_pixels, d_status,
+                          (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *d_in, uint8_t *d_out,
+                    size_t nbytes, void *stream) {
+  if (!aes) return fail(SF_EINVAL, "aes is NULL");
+  if (nbytes == 0) return SF_OK;
+  if (!d_in || !d_out) return fail(SF_EINVAL, "NULL buffer");
+  if (nbytes > (1ull << 40)) return fail(SF_ERANGE, "nbytes too large");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  AesArgs a;
+  make_aes_args(aes, &a);
+  rc = launch_ctr(*ds, a, first_block, d_in, d_out, nbytes, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+}  // extern "C"

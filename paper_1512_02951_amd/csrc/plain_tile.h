@@ -1,0 +1,342 @@
+// Per-tile bodies of the plain (FP32) form, shared by the single-image
+// kernels (plain.hip) and the batched persistent kernel (batch.hip).
+//
+// A tile is 64 consecutive 8x8 blocks of one image, processed by one
+// wavefront with one block per lane.
+//
+// frag_tile: coalesced 8-byte row loads (one row load of a wave covers 512
+// contiguous bytes when the tile lies in one block row), FP32 DCT butterflies
+// in registers, integer private quantiser on the packed pixel words (int8
+// dot products), zigzag split (compile-time for "DC + k AC" selections,
+// wave-uniform branches for any other mask), public coefficients stored
+// straight into the tile-interleaved layout (each store instruction writes
+// 256 contiguous bytes), reconstruction check (the stored values go through
+// the very routine defrag uses; samples that would not round back are
+// appended to the exception list with one atomic per wave), private integers
+// staged in LDS and AES-128-CTR encrypted 16 bytes per lane with coalesced
+// 16-byte stores.
+//
+// defrag_tile: decrypt the tile's private bytes into LDS, gather private and
+// public values in zigzag order, inverse DCT, round half to even, clamp,
+// coalesced 8-byte row stores.
+#pragma once
+
+#include "sf_internal.h"
+
+namespace sf {
+
+struct TileGeom {
+  const uint8_t *pix;
+  uint32_t H, W, Bx, By;
+  uint64_t nb;
+  uint32_t ntiles, npriv, npub;
+  uint64_t mask;
+};
+
+inline TileGeom tile_geom(const Geom &g, const uint8_t *pix) {
+  TileGeom t;
+  t.pix = pix;
+  t.H = g.H;
+  t.W = g.W;
+  t.Bx = g.Bx;
+  t.By = g.By;
+  t.nb = g.nb;
+  t.ntiles = g.ntiles;
+  t.npriv = g.npriv;
+  t.npub = g.npub;
+  t.mask = g.mask;
+  return t;
+}
+
+struct FragOut {
+  float *pub;
+  uint8_t *priv;
+  uint32_t *exc_count, *exc_index;
+  uint8_t *exc_value;
+  uint32_t exc_cap;
+  uint32_t *status;
+  const uint32_t *q2;
+};
+
+struct DefragIn {
+  uint8_t *pix_out;
+  const float *pub;
+  const uint8_t *priv;
+};
+
+// Selection policies.  MaskPrefix<NP>: zigzag positions 0..NP-1 are private
+// (DC + (NP-1) AC), resolved at compile time.  MaskRuntime: any mask, one
+// wave-uniform branch per zigzag position.
+template <int NP>
+struct MaskPrefix {
+  static constexpr bool kStatic = true;
+  static constexpr int kNPriv = NP;
+};
+struct MaskRuntime {
+  static constexpr bool kStatic = false;
+  static constexpr int kNPriv = -1;
+};
+
+__device__ __forceinline__ uint64_t opaque_u64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Calls fpriv(integral_constant<n>, rank) or fpub(integral_constant<n>, rank)
+// for every zigzag position, n = natural index of the position.
+template <class MP, class FP, class FQ>
+__device__ __forceinline__ void for_each_coef(uint64_t mask, FP &&fpriv, FQ &&fpub) {
+  static_for<0, 64>([&](auto zc) {
+    constexpr int z = decltype(zc)::value;
+    constexpr int n = kZigZag.nat[z];
+    if constexpr (MP::kStatic) {
+      if constexpr (z < MP::kNPriv) fpriv(std::integral_constant<int, n>{}, (uint32_t)z);
+      else fpub(std::integral_constant<int, n>{}, (uint32_t)(z - MP::kNPriv));
+    } else {
+      const uint32_t pr = (uint32_t)__builtin_popcountll(mask & ((1ull << z) - 1ull));
+      if ((mask >> z) & 1u) fpriv(std::integral_constant<int, n>{}, pr);
+      else fpub(std::integral_constant<int, n>{}, (uint32_t)z - pr);
+    }
+  });
+}
+
+// Sample offset of row 0 of block b within the image.
+__device__ __forceinline__ uint32_t block_origin(const TileGeom &g, uint32_t b) {
+  const uint32_t per_plane = g.Bx * g.By;
+  const uint32_t c = b / per_plane, rem = b - c * per_plane;
+  const uint32_t by = rem / g.Bx, bx = rem - by * g.Bx;
+  return c * g.H * g.W + by * 8u * g.W + bx * 8u;
+}
+
+// Exclusive prefix sum over the 64 lanes of a wave (and the total).
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, int lane, uint32_t &total) {
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  total = __shfl(incl, 63, 64);
+  return incl - v;
+}
+
+// Orders a wave's LDS writes before its later LDS reads by other lanes (LDS
+// requests of one wave are served in order; this only stops the compiler
+// from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint32_t (&w)[16], int p) { return (w[p / 4] >> (8 * (p % 4))) & 0xffu; }
+
+// AES-CTR over the tile's private byte range [0, tbytes) held in LDS at lp;
+// writes the result to gp.  ctr_first = index of the tile's first AES block
+// in the fragment's counter sequence.
+__device__ __forceinline__ void tile_ctr_store(uint8_t *lp, uint8_t *gp, uint32_t tbytes, int lane, const AesLds &s_aes,
+                                               uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo, uint64_t ctr_first) {
+  const uint32_t nblk = (tbytes + 15u) / 16u;
+  for (uint32_t i = lane; i < nblk; i += 64) {
+    uint4 v = *reinterpret_cast<const uint4 *>(lp + 16u * i);
+    if (enc) {
+      uint32_t w0, w1, w2, w3;
+      aes_counter(ctr_hi, ctr_lo, ctr_first + i, w0, w1, w2, w3);
+      aes_encrypt(w0, w1, w2, w3, s_aes);
+      v.x ^= w0;
+      v.y ^= w1;
+      v.z ^= w2;
+      v.w ^= w3;
+    }
+    if (16u * i + 16u <= tbytes) {
+      *reinterpret_cast<uint4 *>(gp + 16u * i) = v;
+    } else {  // final, partial AES block of the fragment: bytes via LDS
+      *reinterpret_cast<uint4 *>(lp + 16u * i) = v;
+      for (uint32_t j = 16u * i; j < tbytes; ++j) gp[j] = lp[j];
+    }
+  }
+}
+
+// Inverse of tile_ctr_store: global [0, tbytes) -> decrypted bytes in LDS.
+__device__ __forceinline__ void tile_ctr_load(uint8_t *lp, const uint8_t *gp, uint32_t tbytes, int lane,
+                                              const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo,
+                                              uint64_t ctr_first) {
+  const uint32_t nblk = (tbytes + 15u) / 16u;
+  for (uint32_t i = lane; i < nblk; i += 64) {
+    uint4 v;
+    if (16u * i + 16u <= tbytes) {
+      v = *reinterpret_cast<const uint4 *>(gp + 16u * i);
+    } else {  // never read past the end of the fragment
+      for (uint32_t j = 16u * i; j < 16u * i + 16u; ++j) lp[j] = j < tbytes ? gp[j] : (uint8_t)0;
+      v = *reinterpret_cast<const uint4 *>(lp + 16u * i);
+    }
+    if (enc) {
+      uint32_t w0, w1, w2, w3;
+      aes_counter(ctr_hi, ctr_lo, ctr_first + i, w0, w1, w2, w3);
+      aes_encrypt(w0, w1, w2, w3, s_aes);
+      v.x ^= w0;
+      v.y ^= w1;
+      v.z ^= w2;
+      v.w ^= w3;
+    }
+    *reinterpret_cast<uint4 *>(lp + 16u * i) = v;
+  }
+}
+
+template <class MP>
+__device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, uint32_t t, int lane, uint8_t *lp,
+                                          const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo,
+                                          uint64_t ctr_offset, const DctK &K) {
+  const uint64_t b0 = (uint64_t)t * 64u;
+  const uint32_t nt = (uint32_t)min<uint64_t>(64u, g.nb - b0);
+  const bool valid = (uint32_t)lane < nt;
+  const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
+
+  // ---- load the block: 8 rows x 8 bytes
+  uint32_t xs[16];
+  uint32_t org = 0;
+  if (valid) {
+    org = block_origin(g, (uint32_t)b0 + lane);
+    const uint8_t *p = g.pix + org;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(p + (size_t)r * g.W);
+      xs[2 * r] = v.x;
+      xs[2 * r + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int w = 0; w < 16; ++w) xs[w] = 0u;
+  }
+
+  float c[64];
+  static_for<0, 64>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    c[p] = (float)byte_of(xs, p);
+  });
+  uint32_t S = 0;  // block sum, exact
+#pragma unroll
+  for (int w = 0; w < 16; ++w) S = __builtin_amdgcn_udot4(xs[w], 0x01010101u, S, false);
+#pragma unroll
+  for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // now pixels - 128, signed bytes
+
+  fdct8x8(c, K);
+
+  // ---- zigzag split
+  float *pub_tile = o.pub + b0 * g.npub;
+  const cu32_ptr q2 = as_const(o.q2) + opaque_zero();
+  for_each_coef<MP>(
+      mask,
+      [&](auto nc, uint32_t pr) {
+        constexpr int n = decltype(nc)::value;
+        int32_t q;
+        if constexpr (n == 0) {
+          q = (int32_t)((S + 3u + ((S >> 3) & 1u)) >> 3);  // round half even of S / 8
+        } else {
+          q = q2_round(q2_acc(xs, q2 + n * kQ2RowWords));
+        }
+        if (valid) *reinterpret_cast<int16_t *>(lp + 2u * (pr * nt + lane)) = (int16_t)q;
+        c[n] = (float)q;
+      },
+      [&](auto nc, uint32_t pu) {
+        constexpr int n = decltype(nc)::value;
+        if (valid) pub_tile[pu * nt + lane] = c[n];
+      });
+
+  // ---- reconstruction check on exactly the stored values
+  idct8x8(c, K);
+#pragma unroll
+  for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // back to pixel bytes
+  uint32_t nbad = 0;
+  static_for<0, 64>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
+    nbad += (r != (float)byte_of(xs, p)) ? 1u : 0u;
+  });
+  if (!valid) nbad = 0;
+  uint32_t total;
+  const uint32_t before = wave_exclusive_scan(nbad, lane, total);
+  if (total) {  // rare: find the samples again and append them
+    uint32_t first = 0;
+    if (lane == 0) first = atomicAdd(o.exc_count, total);
+    first = __shfl(first, 0, 64);
+    uint32_t slot = first + before;
+    uint64_t bad = 0;
+    static_for<0, 64>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
+      bad |= (r != (float)byte_of(xs, p)) ? (1ull << p) : 0ull;
+    });
+    if (!valid) bad = 0;
+    while (bad) {
+      const uint32_t p = (uint32_t)__builtin_ctzll(bad);
+      bad &= bad - 1ull;
+      const uint32_t idx = org + (p >> 3) * g.W + (p & 7u);
+      if (slot < o.exc_cap) {
+        o.exc_index[slot] = idx;
+        o.exc_value[slot] = g.pix[idx];
+      } else if (o.status) {
+        atomicOr(o.status, SF_STATUS_EXC_OVERFLOW);
+      }
+      ++slot;
+    }
+  }
+
+  // ---- private bytes of the tile: AES-CTR, 16 bytes per lane, coalesced
+  wave_lds_sync();
+  tile_ctr_store(lp, o.priv + b0 * g.npriv * 2u, 2u * g.npriv * nt, lane, s_aes, enc, ctr_hi, ctr_lo,
+                 ctr_offset + b0 * g.npriv / 8u);
+  wave_lds_sync();
+}
+
+template <class MP>
+__device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &in, uint32_t t, int lane, uint8_t *lp,
+                                            const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo,
+                                            uint64_t ctr_offset, const DctK &K) {
+  const uint64_t b0 = (uint64_t)t * 64u;
+  const uint32_t nt = (uint32_t)min<uint64_t>(64u, g.nb - b0);
+  const bool valid = (uint32_t)lane < nt;
+  const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
+
+  tile_ctr_load(lp, in.priv + b0 * g.npriv * 2u, 2u * g.npriv * nt, lane, s_aes, enc, ctr_hi, ctr_lo,
+                ctr_offset + b0 * g.npriv / 8u);
+  wave_lds_sync();
+
+  float c[64];
+  const float *pub_tile = in.pub + b0 * g.npub;
+  for_each_coef<MP>(
+      mask,
+      [&](auto nc, uint32_t pr) {
+        constexpr int n = decltype(nc)::value;
+        c[n] = valid ? (float)*reinterpret_cast<const int16_t *>(lp + 2u * (pr * nt + lane)) : 0.0f;
+      },
+      [&](auto nc, uint32_t pu) {
+        constexpr int n = decltype(nc)::value;
+        c[n] = valid ? pub_tile[pu * nt + lane] : 0.0f;
+      });
+  wave_lds_sync();
+
+  idct8x8(c, K);
+
+  if (valid) {
+    uint8_t *p = in.pix_out + block_origin(g, (uint32_t)b0 + lane);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      uint32_t w[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float v = __builtin_amdgcn_fmed3f(__builtin_rintf(c[8 * r + 4 * h + i]), 0.0f, 255.0f);
+          acc |= (uint32_t)v << (8 * i);
+        }
+        w[h] = acc;
+      }
+      *reinterpret_cast<uint2 *>(p + (size_t)r * g.W) = make_uint2(w[0], w[1]);
+    }
+  }
+}
+
+}  // namespace sf

@@ -1,0 +1,69 @@
+// Internal host-side declarations of the library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sefrag.h"
+#include "sf_device.h"
+
+namespace sf {
+
+// Host-generated constant tables (tables.cpp), independent of any device.
+struct HostTables {
+  uint32_t aes_t0[256];                  // T0[x] = (2S, S, S, 3S) bytes, little-endian word
+  uint8_t sbox[256];                     // FIPS-197 S-box
+  uint32_t q2[64 * kQ2RowWords];         // integer basis limbs, see q2_acc()
+  int32_t q2_int[64 * 64];               // round_half_even(2^20 B[n][p])
+  float cert_m[64];                      // max_p |B[n][p]| (rounded up), per natural index
+  float cert_e[64];                      // 255 * sum_p |Bq/2^20 - B| (rounded up)
+  DctK dct;                              // butterfly constants
+};
+const HostTables &host_tables();
+void aes_expand_key(const uint8_t key[16], uint32_t rk[44]);
+
+// Per-device state: device copies of the tables.
+struct DeviceState {
+  int device = -1;
+  int num_cu = 0;
+  uint32_t *d_aes_t0 = nullptr;
+  uint32_t *d_q2 = nullptr;
+};
+// Lazily initialise the current device; returns SF_OK or an error code.
+int device_state(DeviceState **out);
+
+// Error reporting (thread-local message).
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+// Validated geometry of one image.
+struct Geom {
+  uint32_t H, W, C, Bx, By;
+  uint64_t nb;       // number of 8x8 blocks
+  uint32_t ntiles;   // ceil(nb / 64)
+  uint64_t mask;
+  uint32_t npriv, npub;
+  uint32_t precision;
+};
+int make_geom(const sf_desc *desc, Geom *g);
+
+// AES parameters as passed to kernels.
+struct AesArgs {
+  AesKey key;
+  uint64_t ctr_hi, ctr_lo;
+  uint32_t enabled;
+};
+void make_aes_args(const sf_aes_ctr *aes, AesArgs *a);
+
+// Launchers (plain.hip, aes.hip).
+int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, float *pub, uint8_t *priv,
+                     const sf_exceptions &exc, const AesArgs &aes, uint32_t *status, hipStream_t stream);
+int launch_defrag_fp32(const DeviceState &ds, const Geom &g, const float *pub, const uint8_t *priv,
+                       const sf_exceptions &exc, const AesArgs &aes, uint8_t *pix, uint32_t *status,
+                       hipStream_t stream);
+int launch_ctr(const DeviceState &ds, const AesArgs &aes, uint64_t first_block, const uint8_t *in, uint8_t *out,
+               size_t nbytes, hipStream_t stream);
+
+}  // namespace sf
