@@ -61,11 +61,61 @@ def cpu_baseline(budget_s: float = 20.0):
                       "FP64 direct-sum DCT, integer quantiser, scalar AES-CTR" % (done_px // W, W, C, done_px // 10**6)}
 
 
+def make_sets(sf, synth, torch, dev, nsets, mask, key):
+    sets = []
+    for s in range(nsets):
+        x = synth.image(H, W, C, 2, s, device=dev)
+        fr = sf.frag_image(x, mask, key, synth.ctr0(2, s))
+        y = torch.empty_like(x)
+        sets.append((x, fr, y, synth.ctr0(2, s)))
+    return sets
+
+
+def capture(torch, fn):
+    """Capture fn() (kernel launches on the current stream) into a HIP graph."""
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    return g
+
+
+def time_graphs(torch, graphs, steps, warmup):
+    for i in range(warmup):
+        graphs[i % len(graphs)].replay()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(steps):
+        graphs[i % len(graphs)].replay()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def measure(sf, torch, sets, mask, key, status, steps, warmup):
+    """Round-trip time per step (graph per buffer set: frag + defrag), and the
+    per-launch durations of frag and defrag alone (graphs of one call)."""
+    def rt(x, fr, y, c0):
+        sf.frag_image(x, mask, key, c0, out=fr, status=status)
+        sf.defrag_image(fr, key, c0, out=y, status=status)
+    g_rt = [capture(torch, lambda a=a: rt(*a)) for a in sets]
+    g_f = [capture(torch, lambda a=a: sf.frag_image(a[0], mask, key, a[3], out=a[1], status=status)) for a in sets]
+    g_d = [capture(torch, lambda a=a: sf.defrag_image(a[1], key, a[3], out=a[2], status=status)) for a in sets]
+    ms = time_graphs(torch, g_rt, steps, warmup)
+    frag_ms = time_graphs(torch, g_f, steps, warmup)
+    defrag_ms = time_graphs(torch, g_d, steps, warmup)
+    return ms, frag_ms, defrag_ms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sets", type=int, default=4, help="disjoint buffer sets rotated across steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -83,45 +133,14 @@ def main():
     torch.cuda.set_device(dev)
     mask = sf.prefix_mask(K_PRIV)
     key = synth.aes_key(2)
-    sets = []
-    for s in range(args.sets):
-        x = synth.image(H, W, C, 2, s, device=dev)
-        fr = sf.frag_image(x, mask, key, synth.ctr0(2, s))
-        y = torch.empty_like(x)
-        sets.append((x, fr, y, synth.ctr0(2, s)))
+    sets = make_sets(sf, synth, torch, dev, args.sets, mask, key)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
-
-    def step(i, ev=None):
-        x, fr, y, c0 = sets[i % len(sets)]
-        if ev is not None:
-            ev[0].record()
-        sf.frag_image(x, mask, key, c0, out=fr, status=status)
-        if ev is not None:
-            ev[1].record()
-        sf.defrag_image(fr, key, c0, out=y, status=status)
-        if ev is not None:
-            ev[2].record()
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for i in range(args.steps):
-        step(i, evs[i])
-    stop.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    frag_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    defrag_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    ms, frag_ms, defrag_ms = measure(sf, torch, sets, mask, key, status, args.steps, args.warmup)
     assert int(status.item()) == 0, "device status %d" % status.item()
     for x, fr, y, _ in sets:
         assert torch.equal(x, y), "round trip not exact"
 
-    ms = total_ms / args.steps
     mp = H * W / 1e6
     per_launch = algorithmic_bytes(H, W, C, K_PRIV + 1)
     dom_ms, dom = (frag_ms, "frag") if frag_ms >= defrag_ms else (defrag_ms, "defrag")
@@ -142,7 +161,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "4096x4096 RGB planar uint8, DC+5 AC private (int16, AES-128-CTR), 58 FP32 public "
                                "coefficients per 8x8 block, bit-exact round trip", "images_per_step": 1,
-                   "buffer_sets": len(sets)},
+                   "buffer_sets": len(sets), "launch": "HIP graph per step (frag_image + defrag_image)"},
         "round_trip_GBps": round(round_trip_gbs, 1),
         "hbm_frac_round_trip": round(round_trip_gbs / HBM_PEAK_GBS, 4),
         "frag_ms": round(frag_ms, 5),

@@ -96,15 +96,21 @@ typedef struct sf_aes_ctr {
   uint8_t ctr0[16];
 } sf_aes_ctr;
 
-/* Exception list of the plain (SF_FP32) form: samples whose reconstruction
- * from the stored fragments would not round back to the input.  Written by
- * frag_image (which sets *d_count), read by defrag_image.  Contents beyond the
- * count, and the order of entries, are unspecified. */
+/* Exceptions of the plain (SF_FP32) form: samples whose reconstruction from
+ * the stored fragments would not round back to the input (the report notes
+ * the DCT cannot guarantee losslessness, Sec. 6.4.3/6.8).  They are kept in
+ * per-tile slots of one device buffer of sf_exception_bytes() bytes:
+ *   uint16 count[ntiles]                        (ntiles = ceil(blocks / 64))
+ *   uint16 pos[ntiles][per_tile]   = block-in-tile * 64 + 8*y + x
+ *   uint8  value[ntiles][per_tile] = the sample's value
+ * each part starting on a 16-byte boundary.  frag_image writes every count
+ * (a count above per_tile means slots were lost: SF_STATUS_EXC_OVERFLOW);
+ * defrag_image reads them.  No clearing is needed between calls.
+ * Selections of DC plus at most 4 AC coefficients never produce exceptions;
+ * for them the buffer is neither read nor written and may be NULL. */
 typedef struct sf_exceptions {
-  uint32_t *d_count;  /* device, 1 word: number of exceptions found              */
-  uint32_t *d_index;  /* device, capacity words: sample index c*H*W + y*W + x    */
-  uint8_t *d_value;   /* device, capacity bytes: the sample's value              */
-  uint32_t capacity;  /* entries available in d_index / d_value                  */
+  void *d_buf;        /* device buffer, sf_exception_bytes(desc, per_tile) bytes  */
+  uint32_t per_tile;  /* slots per 64-block tile, 1 .. 4096                      */
 } sf_exceptions;
 
 /* Library version string. */
@@ -120,6 +126,11 @@ const char *sf_last_error(void);
  * Returns SF_OK, SF_EINVAL or SF_ESHAPE. */
 int sf_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private_bytes, size_t *residual_bytes);
 
+/* Byte size of an exception buffer with per_tile slots per tile (host only).
+ * *needed is set to 0 when the selection can never produce exceptions.
+ * Returns SF_OK, SF_EINVAL, SF_ESHAPE or SF_ERANGE (per_tile > 4096). */
+int sf_exception_bytes(const sf_desc *desc, uint32_t per_tile, size_t *bytes, int *needed);
+
 /* Initialise the library on the current HIP device (optional; every entry
  * point does it lazily).  Returns SF_OK, SF_ENOTSUP or SF_EHIP. */
 int sf_init(void);
@@ -130,7 +141,8 @@ int sf_init(void);
  *   d_pixels  : input image, C*H*W bytes.
  *   d_public  : out, public fragment (size from sf_fragment_sizes).
  *   d_private : out, private fragment, encrypted when aes != NULL.
- *   exc       : SF_FP32 only: exception list (may not be NULL for SF_FP32).
+ *   exc       : SF_FP32 only: exception slots; required (non-NULL, with a
+ *               buffer) unless sf_exception_bytes reports them not needed.
  *   d_residual: SF_FP16/SF_BF16 only: out, int8 plane [C][H][W] with
  *               x - clamp(round(reconstruction)) (NULL for SF_FP32).
  *   aes       : key + initial counter, or NULL to leave the private integers

@@ -34,8 +34,7 @@ class SfAesCtr(ctypes.Structure):
 
 
 class SfExceptions(ctypes.Structure):
-    _fields_ = [("d_count", ctypes.c_void_p), ("d_index", ctypes.c_void_p), ("d_value", ctypes.c_void_p),
-                ("capacity", ctypes.c_uint32)]
+    _fields_ = [("d_buf", ctypes.c_void_p), ("per_tile", ctypes.c_uint32)]
 
 
 class SefragError(RuntimeError):
@@ -60,13 +59,15 @@ def lib():
         L.sf_strerror.argtypes = [i32]
         L.sf_last_error.restype = ctypes.c_char_p
         L.sf_fragment_sizes.argtypes = [ctypes.POINTER(SfDesc), ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.sf_exception_bytes.argtypes = [ctypes.POINTER(SfDesc), u32, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_int)]
         L.sf_init.argtypes = []
         L.frag_image.argtypes = [ctypes.POINTER(SfDesc), P, P, P, ctypes.POINTER(SfExceptions), P,
                                  ctypes.POINTER(SfAesCtr), P, P]
         L.defrag_image.argtypes = [ctypes.POINTER(SfDesc), P, P, ctypes.POINTER(SfExceptions), P,
                                    ctypes.POINTER(SfAesCtr), P, P, P]
         L.encrypt_private.argtypes = [ctypes.POINTER(SfAesCtr), u64, P, P, sz, P]
-        for name in ("sf_fragment_sizes", "sf_init", "frag_image", "defrag_image", "encrypt_private"):
+        for name in ("sf_fragment_sizes", "sf_exception_bytes", "sf_init", "frag_image", "defrag_image",
+                     "encrypt_private"):
             getattr(L, name).restype = i32
         _extend(L)
         _lib = L
@@ -126,31 +127,61 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def exception_bytes(H: int, W: int, C: int, mask: int, per_tile: int):
+    """(bytes, needed) of an exception buffer; host only."""
+    d = desc(H, W, C, mask, "fp32")
+    nbytes, needed = ctypes.c_size_t(), ctypes.c_int()
+    check(lib().sf_exception_bytes(ctypes.byref(d), per_tile, ctypes.byref(nbytes), ctypes.byref(needed)))
+    return nbytes.value, bool(needed.value)
+
+
+DEFAULT_PER_TILE = 64
+
+
 @dataclass
 class ExceptionList:
-    """Device exception list of the plain form (count, sample indices, values)."""
-    count: "object"
-    index: "object"
-    value: "object"
+    """Per-tile exception slots of the plain form (one device byte buffer)."""
+    buf: "object"
+    per_tile: int
+    shape: tuple
 
     @staticmethod
-    def empty(capacity: int, device="cuda"):
+    def empty(shape, mask: int, per_tile: int = DEFAULT_PER_TILE, device="cuda"):
         import torch
-        return ExceptionList(torch.zeros(1, dtype=torch.int32, device=device),
-                             torch.zeros(max(capacity, 1), dtype=torch.int32, device=device),
-                             torch.zeros(max(capacity, 1), dtype=torch.uint8, device=device))
-
-    @property
-    def capacity(self) -> int:
-        return self.index.numel()
+        C, H, W = shape
+        nbytes, needed = exception_bytes(H, W, C, mask, per_tile)
+        buf = torch.zeros(max(nbytes, 16), dtype=torch.uint8, device=device) if needed else None
+        return ExceptionList(buf, per_tile, tuple(shape))
 
     def c(self) -> SfExceptions:
-        return SfExceptions(self.count.data_ptr(), self.index.data_ptr(), self.value.data_ptr(), self.capacity)
+        return SfExceptions(self.buf.data_ptr() if self.buf is not None else None, self.per_tile)
 
-
-def default_exception_capacity(n_samples: int) -> int:
-    """A capacity that comfortably covers the exception rates of the plain form."""
-    return max(4096, n_samples // 256)
+    def decode(self):
+        """Host copy of the entries: (sample indices, values, counts per tile)."""
+        import numpy as np
+        C, H, W = self.shape
+        nb = C * H * W // 64
+        nt = (nb + 63) // 64
+        if self.buf is None:
+            return np.zeros(0, np.int64), np.zeros(0, np.uint8), np.zeros(nt, np.int64)
+        raw = self.buf.cpu().numpy()
+        a16 = lambda v: (v + 15) // 16 * 16
+        pos_off = a16(2 * nt)
+        val_off = pos_off + a16(2 * nt * self.per_tile)
+        counts = raw[:2 * nt].view("<u2").astype(np.int64)
+        pos = raw[pos_off:pos_off + 2 * nt * self.per_tile].view("<u2").reshape(nt, self.per_tile)
+        val = raw[val_off:val_off + nt * self.per_tile].reshape(nt, self.per_tile)
+        Bx, By = W // 8, H // 8
+        idx, vals = [], []
+        for t in np.flatnonzero(counts):
+            for e in range(min(counts[t], self.per_tile)):
+                b = 64 * t + int(pos[t, e]) // 64
+                p = int(pos[t, e]) % 64
+                c, rem = divmod(b, Bx * By)
+                by, bx = divmod(rem, Bx)
+                idx.append(c * H * W + (8 * by + p // 8) * W + 8 * bx + p % 8)
+                vals.append(val[t, e])
+        return np.array(idx, np.int64), np.array(vals, np.uint8), counts
 
 
 @dataclass
@@ -181,7 +212,7 @@ def frag_image(pixels, mask: int, key: bytes | None = None, ctr0: bytes | None =
         out = Fragments(
             public=torch.empty(max(pb // esz, 1), dtype=pub_dtype, device=pixels.device),
             private=torch.empty(max(qb, 16), dtype=torch.uint8, device=pixels.device),
-            exceptions=ExceptionList.empty(default_exception_capacity(C * H * W), pixels.device) if prec == "fp32" else None,
+            exceptions=ExceptionList.empty((C, H, W), mask, device=pixels.device) if prec == "fp32" else None,
             residual=torch.empty(rb, dtype=torch.int8, device=pixels.device) if rb else None,
             shape=(C, H, W), mask=mask, precision=prec)
     d = desc(H, W, C, mask, prec)

@@ -40,9 +40,12 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every HIP source into libsefrag.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
+def build(verbose: bool = False, extra=(), out: str | None = None) -> str:
+    """Compile every HIP source into libsefrag.so (always recompiles).
+    ``extra`` adds compiler flags (e.g. -D tuning knobs); ``out`` writes the
+    library elsewhere."""
+    lib = out or LIB
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
            "-o", tmp, *sources()]
     if verbose:
@@ -56,8 +59,8 @@ def build(verbose: bool = False, extra=()) -> str:
         lines = [l for l in proc.stderr.splitlines() if "packed-fp32-ops" not in l]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

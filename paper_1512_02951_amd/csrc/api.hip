@@ -51,6 +51,16 @@ static int check_alignment(const void *pix, const void *pub, const void *priv) {
   return SF_OK;
 }
 
+static size_t align16(size_t v) { return (v + 15u) & ~(size_t)15u; }
+
+ExcLayout exc_layout(const Geom &g, uint32_t per_tile) {
+  ExcLayout L;
+  L.pos_offset = align16((size_t)2 * g.ntiles);
+  L.val_offset = L.pos_offset + align16((size_t)2 * g.ntiles * per_tile);
+  L.total = L.val_offset + align16((size_t)g.ntiles * per_tile);
+  return L;
+}
+
 void make_aes_args(const sf_aes_ctr *aes, AesArgs *a) {
   memset(a, 0, sizeof(*a));
   if (!aes) return;
@@ -135,9 +145,40 @@ int sf_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private
   return SF_OK;
 }
 
+int sf_exception_bytes(const sf_desc *desc, uint32_t per_tile, size_t *bytes, int *needed) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  if (per_tile > kMaxExcPerTile) return fail(SF_ERANGE, "per_tile must be at most 4096");
+  if (bytes) *bytes = exc_layout(g, per_tile).total;
+  if (needed) *needed = mask_needs_check(g.mask) ? 1 : 0;
+  t_last_error.clear();
+  return SF_OK;
+}
+
 int sf_init(void) {
   DeviceState *ds;
   return device_state(&ds);
+}
+
+// Checks shared by frag_image and defrag_image.
+static int check_call(const Geom &g, const void *pix, const void *pub, const void *priv, const sf_exceptions *exc,
+                      const void *residual) {
+  if (!pix || !priv || (g.npub && !pub)) return fail(SF_EINVAL, "NULL fragment or image pointer");
+  int rc = check_alignment(pix, pub, priv);
+  if (rc) return rc;
+  if (g.precision == SF_FP32) {
+    if (mask_needs_check(g.mask)) {
+      if (!exc || !exc->d_buf) return fail(SF_EINVAL, "this selection needs an exception buffer");
+      if (exc->per_tile == 0 || exc->per_tile > kMaxExcPerTile)
+        return fail(SF_ERANGE, "exception slots per tile must be 1 .. 4096");
+      if ((uintptr_t)exc->d_buf & 15u) return fail(SF_EINVAL, "exception buffer must be 16-byte aligned");
+    }
+  } else {
+    if (!residual) return fail(SF_EINVAL, "reduced-precision forms need a residual plane");
+    if ((uintptr_t)residual & 15u) return fail(SF_EINVAL, "residual plane must be 16-byte aligned");
+  }
+  return SF_OK;
 }
 
 int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uint8_t *d_private,
@@ -146,20 +187,15 @@ int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uin
   Geom g;
   int rc = make_geom(desc, &g);
   if (rc) return rc;
-  if (!d_pixels || !d_private || (g.npub && !d_public)) return fail(SF_EINVAL, "NULL fragment or image pointer");
-  if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
-  if (g.precision == SF_FP32) {
-    if (!exc || !exc->d_count || (exc->capacity && (!exc->d_index || !exc->d_value)))
-      return fail(SF_EINVAL, "SF_FP32 needs an exception list");
-  } else {
-    return fail(SF_ENOTSUP, "reduced-precision form not built in this library version");
-  }
-  (void)d_residual;
+  if ((rc = check_call(g, d_pixels, d_public, d_private, exc, d_residual))) return rc;
   DeviceState *ds;
   if ((rc = device_state(&ds))) return rc;
   AesArgs a;
   make_aes_args(aes, &a);
-  rc = launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, *exc, a, d_status, (hipStream_t)stream);
+  if (g.precision == SF_FP32)
+    rc = launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, exc, a, d_status, (hipStream_t)stream);
+  else
+    rc = launch_frag_lp(*ds, g, d_pixels, d_public, d_private, d_residual, a, d_status, (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }
@@ -170,21 +206,15 @@ int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_pri
   Geom g;
   int rc = make_geom(desc, &g);
   if (rc) return rc;
-  if (!d_pixels || !d_private || (g.npub && !d_public)) return fail(SF_EINVAL, "NULL fragment or image pointer");
-  if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
-  if (g.precision == SF_FP32) {
-    if (!exc || !exc->d_count || (exc->capacity && (!exc->d_index || !exc->d_value)))
-      return fail(SF_EINVAL, "SF_FP32 needs an exception list");
-  } else {
-    return fail(SF_ENOTSUP, "reduced-precision form not built in this library version");
-  }
-  (void)d_residual;
+  if ((rc = check_call(g, d_pixels, d_public, d_private, exc, d_residual))) return rc;
   DeviceState *ds;
   if ((rc = device_state(&ds))) return rc;
   AesArgs a;
   make_aes_args(aes, &a);
-  rc = launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, *exc, a, d_pixels, d_status,
-                          (hipStream_t)stream);
+  if (g.precision == SF_FP32)
+    rc = launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, exc, a, d_pixels, (hipStream_t)stream);
+  else
+    rc = launch_defrag_lp(*ds, g, d_public, d_private, d_residual, a, d_pixels, d_status, (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }

@@ -4,21 +4,23 @@
 // A tile is 64 consecutive 8x8 blocks of one image, processed by one
 // wavefront with one block per lane.
 //
-// frag_tile: coalesced 8-byte row loads (one row load of a wave covers 512
+// frag: coalesced 8-byte row loads (one row load of a wave covers 512
 // contiguous bytes when the tile lies in one block row), FP32 DCT butterflies
-// in registers, integer private quantiser on the packed pixel words (int8
-// dot products), zigzag split (compile-time for "DC + k AC" selections,
+// in registers, integer private quantiser on the packed pixel words (int8 dot
+// products), zigzag split (compile-time for "DC + k AC" selections,
 // wave-uniform branches for any other mask), public coefficients stored
 // straight into the tile-interleaved layout (each store instruction writes
-// 256 contiguous bytes), reconstruction check (the stored values go through
-// the very routine defrag uses; samples that would not round back are
-// appended to the exception list with one atomic per wave), private integers
-// staged in LDS and AES-128-CTR encrypted 16 bytes per lane with coalesced
-// 16-byte stores.
+// 256 contiguous bytes), exactness certificate per block and, for the rare
+// waves whose certificate does not rule out a miss, the reconstruction check
+// (the stored values go through the very routine defrag uses; samples that
+// would not round back go to the tile's exception slots, positions found with
+// a wave prefix sum), private integers staged in LDS and AES-128-CTR encrypted
+// 16 bytes per lane with coalesced 16-byte stores.
 //
-// defrag_tile: decrypt the tile's private bytes into LDS, gather private and
+// defrag: decrypt the tile's private bytes into LDS, gather private and
 // public values in zigzag order, inverse DCT, round half to even, clamp,
-// coalesced 8-byte row stores.
+// coalesced 8-byte row stores, then the tile's exceptions (if any) are
+// written by the lanes owning their blocks.
 #pragma once
 
 #include "sf_internal.h"
@@ -48,20 +50,35 @@ inline TileGeom tile_geom(const Geom &g, const uint8_t *pix) {
   return t;
 }
 
+// Exception slots of one image (see sf_exception_bytes): per tile a uint16
+// count, then per_tile uint16 positions (block-in-tile * 64 + sample-in-block)
+// and per_tile uint8 values.
+struct ExcSlots {
+  uint16_t *count;
+  uint16_t *pos;
+  uint8_t *val;
+  uint32_t per_tile;
+  uint32_t check;  // 0: this selection never needs exceptions (nothing read or written)
+};
+
+// Slots of an image's exception buffer (plain.hip); check = 0 when the
+// selection can never need exceptions.
+ExcSlots exc_slots(const Geom &g, const sf_exceptions *exc);
+
 struct FragOut {
   float *pub;
   uint8_t *priv;
-  uint32_t *exc_count, *exc_index;
-  uint8_t *exc_value;
-  uint32_t exc_cap;
+  ExcSlots exc;
   uint32_t *status;
   const uint32_t *q2;
+  float cert_thr;  // a block whose certificate reaches this is checked sample by sample
 };
 
 struct DefragIn {
   uint8_t *pix_out;
   const float *pub;
   const uint8_t *priv;
+  ExcSlots exc;
 };
 
 // Selection policies.  MaskPrefix<NP>: zigzag positions 0..NP-1 are private
@@ -184,21 +201,27 @@ __device__ __forceinline__ void tile_ctr_load(uint8_t *lp, const uint8_t *gp, ui
   }
 }
 
-template <class MP>
-__device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, uint32_t t, int lane, uint8_t *lp,
-                                          const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo,
-                                          uint64_t ctr_offset, const DctK &K) {
-  const uint64_t b0 = (uint64_t)t * 64u;
-  const uint32_t nt = (uint32_t)min<uint64_t>(64u, g.nb - b0);
-  const bool valid = (uint32_t)lane < nt;
-  const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
+// Blocks of tile t: number of blocks and this lane's block origin.
+struct TileLane {
+  uint64_t b0;   // first block of the tile
+  uint32_t nt;   // blocks in the tile (64 except for the last tile)
+  uint32_t valid;  // this lane holds a block (0 or 1)
+  uint32_t org;  // sample offset of the lane's block
+};
 
-  // ---- load the block: 8 rows x 8 bytes
-  uint32_t xs[16];
-  uint32_t org = 0;
-  if (valid) {
-    org = block_origin(g, (uint32_t)b0 + lane);
-    const uint8_t *p = g.pix + org;
+__device__ __forceinline__ TileLane tile_lane(const TileGeom &g, uint32_t t, int lane) {
+  TileLane L;
+  L.b0 = (uint64_t)t * 64u;
+  L.nt = (uint32_t)min<uint64_t>(64u, g.nb - L.b0);
+  L.valid = (uint32_t)lane < L.nt ? 1u : 0u;
+  L.org = L.valid ? block_origin(g, (uint32_t)L.b0 + lane) : 0u;
+  return L;
+}
+
+// The lane's 8x8 block as 16 words (row r = words 2r, 2r+1), zero if no block.
+__device__ __forceinline__ void load_block(const TileGeom &g, const TileLane &L, uint32_t (&xs)[16]) {
+  if (L.valid) {
+    const uint8_t *p = g.pix + L.org;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const uint2 v = *reinterpret_cast<const uint2 *>(p + (size_t)r * g.W);
@@ -209,6 +232,16 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
 #pragma unroll
     for (int w = 0; w < 16; ++w) xs[w] = 0u;
   }
+}
+
+template <class MP>
+__device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, uint32_t t, const TileLane &L,
+                                          uint32_t (&xs)[16], int lane, uint8_t *lp, const AesLds &s_aes, uint32_t enc,
+                                          uint64_t ctr_hi, uint64_t ctr_lo, const DctK &K) {
+  const uint64_t b0 = L.b0;
+  const uint32_t nt = L.nt;
+  const bool valid = L.valid != 0u;
+  const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
 
   float c[64];
   static_for<0, 64>([&](auto pc) {
@@ -226,6 +259,9 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
   // ---- zigzag split
   float *pub_tile = o.pub + b0 * g.npub;
   const cu32_ptr q2 = as_const(o.q2) + opaque_zero();
+  // cert = sum over private n of (|q_n - acc_n / 2^20| + E_n) * M_n bounds how far
+  // the private rounding moves any reconstructed sample (table words kQ2Cert*).
+  float cert = 0.0f;
   for_each_coef<MP>(
       mask,
       [&](auto nc, uint32_t pr) {
@@ -233,8 +269,15 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
         int32_t q;
         if constexpr (n == 0) {
           q = (int32_t)((S + 3u + ((S >> 3) & 1u)) >> 3);  // round half even of S / 8
+          const int32_t d = 8 * q - (int32_t)S;                // 8 (q - S/8), exact
+          cert += (float)(d < 0 ? -d : d) * (0.125f * 0.125f);  // M_0 = 1/8, E_0 = 0
         } else {
-          q = q2_round(q2_acc(xs, q2 + n * kQ2RowWords));
+          const cu32_ptr row = q2 + n * kQ2RowWords;
+          const int32_t acc = q2_acc(xs, row);
+          q = q2_round(acc);
+          const int32_t d = (int32_t)((uint32_t)q << 20) - acc;  // |d| <= 2^19
+          const float e = __builtin_fmaf((float)(d < 0 ? -d : d), 0x1p-20f, __uint_as_float(row[kQ2CertE]));
+          cert = __builtin_fmaf(e, __uint_as_float(row[kQ2CertM]), cert);
         }
         if (valid) *reinterpret_cast<int16_t *>(lp + 2u * (pr * nt + lane)) = (int16_t)q;
         c[n] = (float)q;
@@ -244,63 +287,55 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
         if (valid) pub_tile[pu * nt + lane] = c[n];
       });
 
-  // ---- reconstruction check on exactly the stored values
-  idct8x8(c, K);
+  // ---- reconstruction check on exactly the stored values, for waves holding
+  // a block whose certificate does not rule out a miss
+  if (o.exc.check) {
+    uint32_t total = 0;
+    if (__ballot(valid && cert >= o.cert_thr) != 0ull) {
+      idct8x8(c, K);
 #pragma unroll
-  for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // back to pixel bytes
-  uint32_t nbad = 0;
-  static_for<0, 64>([&](auto pc) {
-    constexpr int p = decltype(pc)::value;
-    const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
-    nbad += (r != (float)byte_of(xs, p)) ? 1u : 0u;
-  });
-  if (!valid) nbad = 0;
-  uint32_t total;
-  const uint32_t before = wave_exclusive_scan(nbad, lane, total);
-  if (total) {  // rare: find the samples again and append them
-    uint32_t first = 0;
-    if (lane == 0) first = atomicAdd(o.exc_count, total);
-    first = __shfl(first, 0, 64);
-    uint32_t slot = first + before;
-    uint64_t bad = 0;
-    static_for<0, 64>([&](auto pc) {
-      constexpr int p = decltype(pc)::value;
-      const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
-      bad |= (r != (float)byte_of(xs, p)) ? (1ull << p) : 0ull;
-    });
-    if (!valid) bad = 0;
-    while (bad) {
-      const uint32_t p = (uint32_t)__builtin_ctzll(bad);
-      bad &= bad - 1ull;
-      const uint32_t idx = org + (p >> 3) * g.W + (p & 7u);
-      if (slot < o.exc_cap) {
-        o.exc_index[slot] = idx;
-        o.exc_value[slot] = g.pix[idx];
-      } else if (o.status) {
-        atomicOr(o.status, SF_STATUS_EXC_OVERFLOW);
+      for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // back to pixel bytes
+      uint64_t bad = 0;
+      static_for<0, 64>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
+        bad |= (r != (float)byte_of(xs, p)) ? (1ull << p) : 0ull;
+      });
+      if (!valid) bad = 0;
+      uint32_t slot = wave_exclusive_scan((uint32_t)__builtin_popcountll(bad), lane, total);
+      while (bad) {
+        const uint32_t p = (uint32_t)__builtin_ctzll(bad);
+        bad &= bad - 1ull;
+        if (slot < o.exc.per_tile) {
+          const size_t e = (size_t)t * o.exc.per_tile + slot;
+          o.exc.pos[e] = (uint16_t)(lane * 64 + p);
+          o.exc.val[e] = g.pix[L.org + (p >> 3) * g.W + (p & 7u)];
+        }
+        ++slot;
       }
-      ++slot;
+      if (total > o.exc.per_tile && o.status && lane == 0) atomicOr(o.status, SF_STATUS_EXC_OVERFLOW);
     }
+    if (lane == 0) o.exc.count[t] = (uint16_t)(total < 65535u ? total : 65535u);
   }
 
   // ---- private bytes of the tile: AES-CTR, 16 bytes per lane, coalesced
   wave_lds_sync();
   tile_ctr_store(lp, o.priv + b0 * g.npriv * 2u, 2u * g.npriv * nt, lane, s_aes, enc, ctr_hi, ctr_lo,
-                 ctr_offset + b0 * g.npriv / 8u);
+                 b0 * g.npriv / 8u);
   wave_lds_sync();
 }
 
 template <class MP>
-__device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &in, uint32_t t, int lane, uint8_t *lp,
-                                            const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo,
-                                            uint64_t ctr_offset, const DctK &K) {
-  const uint64_t b0 = (uint64_t)t * 64u;
-  const uint32_t nt = (uint32_t)min<uint64_t>(64u, g.nb - b0);
-  const bool valid = (uint32_t)lane < nt;
+__device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &in, uint32_t t, const TileLane &L,
+                                            int lane, uint8_t *lp, const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi,
+                                            uint64_t ctr_lo, const DctK &K) {
+  const uint64_t b0 = L.b0;
+  const uint32_t nt = L.nt;
+  const bool valid = L.valid != 0u;
   const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
 
   tile_ctr_load(lp, in.priv + b0 * g.npriv * 2u, 2u * g.npriv * nt, lane, s_aes, enc, ctr_hi, ctr_lo,
-                ctr_offset + b0 * g.npriv / 8u);
+                b0 * g.npriv / 8u);
   wave_lds_sync();
 
   float c[64];
@@ -319,8 +354,8 @@ __device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &i
 
   idct8x8(c, K);
 
+  uint8_t *p = in.pix_out + L.org;
   if (valid) {
-    uint8_t *p = in.pix_out + block_origin(g, (uint32_t)b0 + lane);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       uint32_t w[2];
@@ -335,6 +370,17 @@ __device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &i
         w[h] = acc;
       }
       *reinterpret_cast<uint2 *>(p + (size_t)r * g.W) = make_uint2(w[0], w[1]);
+    }
+  }
+  // ---- the tile's exceptions, written by the lane that stored the block
+  // (same thread, later store to the same address)
+  if (in.exc.check) {
+    const uint32_t n = in.exc.count[t];
+    const uint32_t m = n < in.exc.per_tile ? n : in.exc.per_tile;
+    for (uint32_t e = 0; e < m; ++e) {
+      const size_t k = (size_t)t * in.exc.per_tile + e;
+      const uint32_t pos = in.exc.pos[k];
+      if (valid && (pos >> 6) == (uint32_t)lane) p[((pos >> 3) & 7u) * g.W + (pos & 7u)] = in.exc.val[k];
     }
   }
 }

@@ -125,8 +125,12 @@ __device__ __forceinline__ void idct8x8(float (&c)[64], const DctK &K) {
 // |acc| <= 2040 * 2^20 < 2^31 fits, so the wrapped value is exact.
 // Table row layout (kQ2RowWords words per natural index n):
 //   [0,16) limb l, [16,32) limb m, [32,48) limb h (4 signed bytes per word,
-//   byte i of word w is pixel p = 4w + i), [48] = 128 * sum_p Bq[n][p].
+//   byte i of word w is pixel p = 4w + i), [48] = 128 * sum_p Bq[n][p],
+//   [49] = E_n as float bits: 255 * sum_p |Bq[n][p]/2^20 - B[n][p]| (>= |acc/2^20 - C_n|),
+//   [50] = M_n as float bits: max_p |B[n][p]| (both rounded up).
 constexpr int kQ2RowWords = 52;
+constexpr int kQ2CertE = 49;
+constexpr int kQ2CertM = 50;
 
 // Read-only tables are read through constant-address-space pointers so that
 // wave-uniform reads become scalar loads into SGPRs.

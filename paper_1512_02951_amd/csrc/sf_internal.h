@@ -23,6 +23,10 @@ struct HostTables {
 };
 const HostTables &host_tables();
 void aes_expand_key(const uint8_t key[16], uint32_t rk[44]);
+// Certificate threshold and whether a selection can ever need the
+// reconstruction check (false for DC + up to 4 AC).
+float cert_threshold();
+bool mask_needs_check(uint64_t mask);
 
 // Per-device state: device copies of the tables.
 struct DeviceState {
@@ -57,12 +61,26 @@ struct AesArgs {
 };
 void make_aes_args(const sf_aes_ctr *aes, AesArgs *a);
 
+// Byte layout of an exception buffer: uint16 count per tile, then
+// per_tile uint16 positions and per_tile uint8 values per tile, each part
+// padded to 16 bytes.
+struct ExcLayout {
+  size_t pos_offset, val_offset, total;
+};
+ExcLayout exc_layout(const Geom &g, uint32_t per_tile);
+constexpr uint32_t kMaxExcPerTile = 4096;
+
 // Launchers (plain.hip, aes.hip).
 int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, float *pub, uint8_t *priv,
-                     const sf_exceptions &exc, const AesArgs &aes, uint32_t *status, hipStream_t stream);
+                     const sf_exceptions *exc, const AesArgs &aes, uint32_t *status, hipStream_t stream);
 int launch_defrag_fp32(const DeviceState &ds, const Geom &g, const float *pub, const uint8_t *priv,
-                       const sf_exceptions &exc, const AesArgs &aes, uint8_t *pix, uint32_t *status,
-                       hipStream_t stream);
+                       const sf_exceptions *exc, const AesArgs &aes, uint8_t *pix, hipStream_t stream);
+// Reduced-precision (MFMA fp16 / bf16 + int8 residual) form (lp.hip).
+int launch_frag_lp(const DeviceState &ds, const Geom &g, const uint8_t *pix, void *pub, uint8_t *priv,
+                   int8_t *residual, const AesArgs &aes, uint32_t *status, hipStream_t stream);
+int launch_defrag_lp(const DeviceState &ds, const Geom &g, const void *pub, const uint8_t *priv,
+                     const int8_t *residual, const AesArgs &aes, uint8_t *pix, uint32_t *status,
+                     hipStream_t stream);
 int launch_ctr(const DeviceState &ds, const AesArgs &aes, uint64_t first_block, const uint8_t *in, uint8_t *out,
                size_t nbytes, hipStream_t stream);
 

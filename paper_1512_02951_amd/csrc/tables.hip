@@ -91,6 +91,8 @@ void build_dct(HostTables &t) {
         row[32 + w] |= (uint32_t)(uint8_t)(int8_t)h << sh;
       }
       row[48] = (uint32_t)(int32_t)(128 * rowsum);
+      memcpy(&row[kQ2CertE], &t.cert_e[n], 4);
+      memcpy(&row[kQ2CertM], &t.cert_m[n], 4);
     }
 }
 
@@ -105,6 +107,28 @@ const HostTables &host_tables() {
     build_dct(g_tables);
   });
   return g_tables;
+}
+
+// Floating-point allowance of the certificate: bounds the effect on any
+// reconstructed sample of (a) the FP32 error of the stored public
+// coefficients and (b) the FP32 evaluation error of the inverse transform.
+// With u = 2^-24 and every butterfly output at most 6 roundings away from
+// exact, per coefficient |dC| <= 2*8*255*6u*(1+6u) ~ 1.46e-3, so (a) <=
+// 8 * 1.46e-3 (sum_n |B_n(p)| <= 8) and (b) <= 2*6u*sum_n |B_n(p)||c_n| <=
+// 2.9e-3; 1/32 leaves a factor of two.  2^-12 covers the FP32 evaluation of
+// the certificate sum itself.
+float cert_threshold() { return 0.5f - 0x1p-5f - 0x1p-12f; }
+
+bool mask_needs_check(uint64_t mask) {
+  const HostTables &t = host_tables();
+  static constexpr ZigZag zz{};
+  double worst = 0.0;
+  for (int z = 0; z < 64; ++z)
+    if ((mask >> z) & 1u) {
+      const int n = zz.nat[z];
+      worst += (0.5 + (n == 0 ? 0.0 : (double)t.cert_e[n])) * (double)t.cert_m[n];
+    }
+  return worst >= (double)cert_threshold();
 }
 
 void aes_expand_key(const uint8_t key[16], uint32_t rk[44]) {

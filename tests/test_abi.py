@@ -66,7 +66,7 @@ def test_descriptor_validation(H, W, C, mask, prec, code):
     assert L.sf_fragment_sizes(ctypes.byref(d), ctypes.byref(out), None, None) == code
     assert L.sf_last_error()
     # frag/defrag validate before any device call
-    exc = sf.SfExceptions(8, 16, 32, 1)
+    exc = sf.SfExceptions(64, 1)
     assert L.frag_image(ctypes.byref(d), 64, 64, 64, ctypes.byref(exc), None, None, None, None) == code
     assert L.defrag_image(ctypes.byref(d), 64, 64, ctypes.byref(exc), None, None, 64, None, None) == code
 
@@ -74,16 +74,29 @@ def test_descriptor_validation(H, W, C, mask, prec, code):
 def test_null_and_alignment_checks():
     L = sf.lib()
     d = sf.SfDesc(8, 8, 1, 0, 0x3F)
-    exc = sf.SfExceptions(64, 64, 64, 4)
+    exc = sf.SfExceptions(64, 4)
     assert L.frag_image(None, 64, 64, 64, ctypes.byref(exc), None, None, None, None) == sf.SF_EINVAL
     assert L.frag_image(ctypes.byref(d), None, 64, 64, ctypes.byref(exc), None, None, None, None) == sf.SF_EINVAL
     assert L.frag_image(ctypes.byref(d), 64, 64, 64, None, None, None, None, None) == sf.SF_EINVAL
+    bad = sf.SfExceptions(64, 5000)
+    assert L.frag_image(ctypes.byref(d), 64, 64, 64, ctypes.byref(bad), None, None, None, None) == sf.SF_ERANGE
+    lp = sf.SfDesc(8, 8, 1, sf.SF_FP16, 0x3F)
+    assert L.frag_image(ctypes.byref(lp), 64, 64, 64, None, None, None, None, None) == sf.SF_EINVAL  # no residual
     assert L.frag_image(ctypes.byref(d), 65, 64, 64, ctypes.byref(exc), None, None, None, None) == sf.SF_EINVAL
     assert L.frag_image(ctypes.byref(d), 64, 64, 72, ctypes.byref(exc), None, None, None, None) == sf.SF_EINVAL
     assert L.encrypt_private(None, 0, 64, 64, 16, None) == sf.SF_EINVAL
     a = sf.SfAesCtr()
     assert L.encrypt_private(ctypes.byref(a), 0, None, 64, 16, None) == sf.SF_EINVAL
     assert L.encrypt_private(ctypes.byref(a), 0, 64, 64, 0, None) == sf.SF_OK
+
+
+def test_exception_buffer_layout_size():
+    # 4096x4096 RGB: 12288 tiles; counts 24576 B, positions 2*12288*64, values 12288*64
+    nbytes, needed = sf.exception_bytes(4096, 4096, 3, sf.prefix_mask(5), 64)
+    assert needed and nbytes == 24576 + 2 * 12288 * 64 + 12288 * 64
+    assert not sf.exception_bytes(4096, 4096, 3, sf.prefix_mask(4), 64)[1]
+    with pytest.raises(sf.SefragError):
+        sf.exception_bytes(64, 64, 1, 3, 4097)
 
 
 def test_error_strings():
