@@ -62,6 +62,7 @@ def _lib():
         lib.orc_aes_expand.argtypes = [P, P]
         lib.orc_aes128_encrypt.argtypes = [P, P, P]
         lib.orc_ctr_xor.argtypes = [P, P, u64, P, P, i64]
+        lib.orc_ctr_keystream.argtypes = [P, P, P, i64, P]
         lib.orc_frag.argtypes = [P, i32, i32, i32, u64, P, P, P, P, P, P, P, i64, P]
         lib.orc_frag.restype = i64
         lib.orc_defrag.argtypes = [i32, i32, i32, u64, P, P, P, P, P, P, P, i64, P]
@@ -203,6 +204,24 @@ def ctr_xor(key: bytes, ctr0: bytes, data, first_block: int = 0) -> np.ndarray:
     out = np.zeros_like(d)
     _lib().orc_ctr_xor(_ptr(k), _ptr(c), first_block, _ptr(d), _ptr(out), d.size)
     return out
+
+
+def ctr_keystream(key: bytes, ctr0: bytes, block_indices) -> np.ndarray:
+    """(n, 16) keystream blocks E_K(ctr0 + i) for the given block indices."""
+    k = np.frombuffer(bytes(key), np.uint8).copy()
+    c = np.frombuffer(bytes(ctr0), np.uint8).copy()
+    idx = np.ascontiguousarray(block_indices, dtype=np.uint64)
+    out = np.zeros((idx.size, 16), np.uint8)
+    _lib().orc_ctr_keystream(_ptr(k), _ptr(c), _ptr(idx), idx.size, _ptr(out))
+    return out
+
+
+def tile_offsets(nb: int, P: int, blocks, j) -> np.ndarray:
+    """Vector form of tile_offset (same index formula) for arrays of blocks / values."""
+    b = np.asarray(blocks, np.int64)
+    t = b // 64
+    nt = np.minimum(64, nb - 64 * t)
+    return 64 * t * P + np.asarray(j, np.int64) * nt + b % 64
 
 
 # ---------------------------------------------------------------- pipeline

@@ -456,3 +456,17 @@ int orc_get_threads(void) {
   return 1;
 #endif
 }
+
+/* Keystream blocks E_K(ctr0 + idx[i]) for a list of block indices (CTR
+ * definition of SP 800-38A, as orc_ctr_xor); out holds 16 bytes per index. */
+void orc_ctr_keystream(const uint8_t key[16], const uint8_t ctr0[16], const uint64_t *idx, int64_t n, uint8_t *out) {
+  uint8_t rk[176], sbox[256];
+  orc_aes_expand(key, rk);
+  orc_aes_sbox(sbox);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    uint8_t T[16];
+    orc_ctr_block(ctr0, idx[i], T);
+    orc_aes_encrypt_rk(rk, sbox, T, out + 16 * i);
+  }
+}

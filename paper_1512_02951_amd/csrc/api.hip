@@ -90,21 +90,28 @@ int device_state(DeviceState **out) {
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return fail(SF_ENOTSUP, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
     const HostTables &t = host_tables();
-    uint32_t *d_t0 = nullptr, *d_q2 = nullptr;
-    if ((e = hipMalloc(&d_t0, sizeof(t.aes_t0))) != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
-    if ((e = hipMalloc(&d_q2, sizeof(t.q2))) != hipSuccess) {
-      (void)hipFree(d_t0);
+    uint32_t *d_t0 = nullptr, *d_q2 = nullptr, *d_lp = nullptr;
+    auto release = [&] {
+      if (d_t0) (void)hipFree(d_t0);
+      if (d_q2) (void)hipFree(d_q2);
+      if (d_lp) (void)hipFree(d_lp);
+    };
+    if ((e = hipMalloc(&d_t0, sizeof(t.aes_t0))) != hipSuccess || (e = hipMalloc(&d_q2, sizeof(t.q2))) != hipSuccess ||
+        (e = hipMalloc(&d_lp, sizeof(t.lp))) != hipSuccess) {
+      release();
       return hip_fail(e, "hipMalloc(tables)");
     }
     if ((e = hipMemcpy(d_t0, t.aes_t0, sizeof(t.aes_t0), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_q2, t.q2, sizeof(t.q2), hipMemcpyHostToDevice)) != hipSuccess) {
-      (void)hipFree(d_t0);
-      (void)hipFree(d_q2);
+        (e = hipMemcpy(d_q2, t.q2, sizeof(t.q2), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_lp, t.lp, sizeof(t.lp), hipMemcpyHostToDevice)) != hipSuccess) {
+      release();
       return hip_fail(e, "hipMemcpy(tables)");
     }
     s.num_cu = prop.multiProcessorCount;
+    s.max_lds_per_block = prop.sharedMemPerBlock;
     s.d_aes_t0 = d_t0;
     s.d_q2 = d_q2;
+    s.d_lp = d_lp;
     s.device = dev;
   }
   *out = &s;

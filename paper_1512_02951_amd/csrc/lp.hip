@@ -1,16 +1,525 @@
-// Reduced-precision form (fp16 / bf16 MFMA transforms with an int8 residual plane).
-#include "sf_internal.h"
+// Reduced-precision form: the 8x8 DCT and inverse DCT as 64x64 basis
+// contractions on the matrix cores (v_mfma_f32_32x32x16_{f16,bf16}, FP32
+// accumulation), public coefficients stored as fp16 or bf16, private
+// integers exactly as in the plain form, and a dense int8 residual plane
+// r = x - clamp(round(IDCT(stored fragments))) that makes the round trip
+// bit-exact.  frag computes the reconstruction with the same routine and the
+// same operands defrag uses, so both see the same value bit for bit.
+//
+// One wavefront per tile of 64 blocks, processed as two 32-block halves
+// (the N dimension of the MFMA).  Forward: C^T = K X^T with M = coefficient,
+// N = block, K = pixel; inverse: X^T = K^T C^T with M = pixel.  bf16 keeps
+// the basis as a hi + lo pair (and splits the private integers, which bf16
+// cannot hold exactly) so the transforms stay close to FP32 accuracy.
+#include <string.h>
+
+#include "plain_tile.h"
 
 namespace sf {
 
-int launch_frag_lp(const DeviceState &, const Geom &, const uint8_t *, void *, uint8_t *, int8_t *, const AesArgs &,
-                   uint32_t *, hipStream_t) {
-  return fail(SF_ENOTSUP, "reduced-precision form not built yet");
+// ---------------------------------------------------------------------------
+// Host: basis operand tables in per-lane order.
+namespace {
+
+uint16_t f16_bits(double v) {
+  const _Float16 h = (_Float16)v;
+  uint16_t b;
+  memcpy(&b, &h, 2);
+  return b;
+}
+float f16_value(uint16_t b) {
+  _Float16 h;
+  memcpy(&h, &b, 2);
+  return (float)h;
+}
+uint16_t bf16_bits(double v) {  // round to nearest even, via float
+  const float f = (float)v;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
 }
 
-int launch_defrag_lp(const DeviceState &, const Geom &, const void *, const uint8_t *, const int8_t *,
-                     const AesArgs &, uint8_t *, uint32_t *, hipStream_t) {
-  return fail(SF_ENOTSUP, "reduced-precision form not built yet");
+}  // namespace
+
+// Table layout: word ((mt * 4 + s) * 64 + lane) * 4 + w holds elements
+// e = 2w, 2w+1 of lane `lane` for M-tile mt and K-step s, i.e. the A operand
+// of v_mfma_f32_32x32x16: row i = 32 mt + lane % 32, columns
+// k = 16 s + 8 (lane / 32) + e.  Forward tables: A[i][k] = B[n = i][p = k];
+// inverse tables: A[i][k] = B[n = k][p = i].
+void build_lp_tables(const double *basis, uint32_t (*lp)[kLpTableWords]) {
+  for (int inv = 0; inv < 2; ++inv)
+    for (int mt = 0; mt < 2; ++mt)
+      for (int s = 0; s < 4; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int i = 32 * mt + (l & 31), k = 16 * s + 8 * (l >> 5) + e;
+            const double v = inv ? basis[k * 64 + i] : basis[i * 64 + k];
+            const uint16_t h16 = f16_bits(v);
+            const uint16_t hb = bf16_bits(v);
+            const uint16_t lb = bf16_bits(v - bf16_value(hb));
+            (void)f16_value;
+            const int word = ((mt * 4 + s) * 64 + l) * 4 + e / 2, sh = 16 * (e & 1);
+            auto put = [&](int table, uint16_t bits) {
+              if (sh == 0) lp[table][word] = 0u;
+              lp[table][word] |= (uint32_t)bits << sh;
+            };
+            put(inv ? 1 : 0, h16);
+            put(inv ? 4 : 2, hb);
+            put(inv ? 5 : 3, lb);
+          }
+}
+
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+template <bool BF>
+__device__ __forceinline__ f32x16 mfma(const uint4 &a, const uint4 &b, const f32x16 &c) {
+  if constexpr (BF)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0, 0,
+                                                  0);
+}
+
+// 16-bit storage encodings (round to nearest even).
+template <bool BF>
+__device__ __forceinline__ uint32_t to16(float v) {
+  if constexpr (BF) return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v);
+  else return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+}
+template <bool BF>
+__device__ __forceinline__ float from16(uint32_t b) {
+  if constexpr (BF) return __uint_as_float(b << 16);
+  else return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+}
+
+// Eight pixel bytes -> eight exact 16-bit values.
+template <bool BF>
+__device__ __forceinline__ uint4 pixels16(uint2 px) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t src = i < 2 ? px.x : px.y;
+    const float a = (float)((src >> (16 * (i & 1))) & 0xffu), b = (float)((src >> (16 * (i & 1) + 8)) & 0xffu);
+    w[i] = to16<BF>(a) | (to16<BF>(b) << 16);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Operand tables in LDS (copied once per workgroup): per table
+// 2 x 4 x 64 lanes x 16 bytes.
+// f16: forward, inverse; bf16: forward hi, forward lo, inverse hi, inverse lo.
+template <bool BF>
+struct LpLds {
+  static constexpr int kFwd = 0, kFwdLo = 1, kInv = BF ? 2 : 1, kInvLo = 3;
+  uint4 t[BF ? 4 : 2][2 * 4 * 64];
+};
+
+template <bool BF>
+__device__ __forceinline__ const uint4 &op(const LpLds<BF> &L, int table, int mt, int s, int lane) {
+  return L.t[table][(mt * 4 + s) * 64 + lane];
+}
+
+// The one reconstruction routine: y[mt] (pixels 32 mt .. 32 mt + 31 of the
+// lane's block column) = sum over K-steps of inverse basis x coefficients.
+template <bool BF>
+__device__ __forceinline__ void lp_idct(const LpLds<BF> &L, int lane, const uint4 (&chi)[4], const uint4 (&clo)[4],
+                                        f32x16 (&y)[2]) {
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc = mfma<BF>(op(L, LpLds<BF>::kInv, mt, s, lane), chi[s], acc);
+      if constexpr (BF) {
+        acc = mfma<BF>(op(L, LpLds<BF>::kInvLo, mt, s, lane), chi[s], acc);
+        acc = mfma<BF>(op(L, LpLds<BF>::kInv, mt, s, lane), clo[s], acc);
+      }
+    }
+    y[mt] = acc;
+  }
+}
+
+// Rank bookkeeping for natural index n under a runtime mask (wave-uniform).
+struct CoefSlot {
+  uint32_t priv;  // 1 if private
+  uint32_t rank;  // rank among the private (priv) or public (!priv) positions
+};
+__device__ __forceinline__ CoefSlot coef_slot(uint64_t mask, int n) {
+  const int z = kZigZagInv.pos[n];
+  const uint32_t before = (uint32_t)__builtin_popcountll(mask & ((1ull << z) - 1ull));
+  CoefSlot c;
+  c.priv = (uint32_t)((mask >> z) & 1u);
+  c.rank = c.priv ? before : (uint32_t)z - before;
+  return c;
+}
+
+// Private integer of natural index n -> (hi, lo) 16-bit operand pair.
+template <bool BF>
+__device__ __forceinline__ void split_int(int32_t q, uint32_t &hi, uint32_t &lo) {
+  hi = to16<BF>((float)q);
+  lo = BF ? to16<BF>((float)q - from16<BF>(hi)) : 0u;
+}
+
+struct LpFragArgs {
+  TileGeom g;
+  uint16_t *pub;
+  uint8_t *priv;
+  int8_t *resid;
+  uint32_t *status;
+  const uint32_t *q2;
+  const uint32_t *tables;  // kLpTables x kLpTableWords
+  const uint32_t *aes_t0;
+  AesArgs aes;
+  uint32_t lds_priv_bytes;
+  uint32_t plist[16];      // natural indices of the private positions, 4 per word
+};
+
+struct LpDefragArgs {
+  TileGeom g;
+  const uint16_t *pub;
+  const uint8_t *priv;
+  const int8_t *resid;
+  uint8_t *pix_out;
+  uint32_t *status;
+  const uint32_t *tables;
+  const uint32_t *aes_t0;
+  AesArgs aes;
+  uint32_t lds_priv_bytes;
+};
+
+template <bool BF>
+__device__ __forceinline__ void load_lp_tables(LpLds<BF> &L, const uint32_t *tables, int tid) {
+  const uint4 *src = reinterpret_cast<const uint4 *>(tables);
+  constexpr int kWords4 = kLpTableWords / 4;  // uint4 per table
+  for (int i = tid; i < kWords4; i += kThreads) {
+    if constexpr (BF) {
+      L.t[0][i] = src[2 * kWords4 + i];
+      L.t[1][i] = src[3 * kWords4 + i];
+      L.t[2][i] = src[4 * kWords4 + i];
+      L.t[3][i] = src[5 * kWords4 + i];
+    } else {
+      L.t[0][i] = src[0 * kWords4 + i];
+      L.t[1][i] = src[1 * kWords4 + i];
+    }
+  }
+}
+
+template <bool BF>
+__global__ __launch_bounds__(kThreads) void frag_lp_kernel(LpFragArgs a) {
+  __shared__ AesLds s_aes;
+  __shared__ LpLds<BF> s_tab;
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
+  load_lp_tables<BF>(s_tab, a.tables, threadIdx.x);
+  __syncthreads();
+  uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
+  const TileGeom &g = a.g;
+  const uint64_t mask = opaque_u64(g.mask);
+  const uint32_t h = (uint32_t)lane >> 5, jl = (uint32_t)lane & 31u;
+  const uint32_t stride = gridDim.x * kWaves;
+  uint32_t rflag = 0;
+
+  for (uint32_t t = blockIdx.x * kWaves + wave; t < g.ntiles; t += stride) {
+    const TileLane L = tile_lane(g, t, lane);
+    const uint64_t b0 = L.b0;
+    const uint32_t ntb = L.nt;
+
+    // ---- private integers, one block per lane (as in the plain form)
+    {
+      uint32_t xs[16];
+      load_block(g, L, xs);
+      uint32_t S = 0;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) S = __builtin_amdgcn_udot4(xs[w], 0x01010101u, S, false);
+#pragma unroll
+      for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;
+      const cu32_ptr q2 = as_const(a.q2) + opaque_zero();
+      for (uint32_t i = 0; i < g.npriv; ++i) {
+        const uint32_t n = (a.plist[i >> 2] >> (8 * (i & 3))) & 0xffu;
+        int32_t q;
+        if (n == 0) q = (int32_t)((S + 3u + ((S >> 3) & 1u)) >> 3);
+        else q = q2_round(q2_acc(xs, q2 + n * kQ2RowWords));
+        if (L.valid) *reinterpret_cast<int16_t *>(lp + 2u * (i * ntb + lane)) = (int16_t)q;
+      }
+    }
+    wave_lds_sync();
+
+    uint16_t *pub_tile = a.pub + b0 * g.npub;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const uint32_t jb = 32u * nt + jl;
+      const bool bv = jb < ntb;
+      const uint32_t borg = bv ? block_origin(g, (uint32_t)b0 + jb) : 0u;
+
+      // ---- forward transform: C^T = K X^T
+      uint4 bx[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        uint2 px = make_uint2(0u, 0u);
+        if (bv) px = *reinterpret_cast<const uint2 *>(g.pix + borg + (size_t)(2 * s + h) * g.W);
+        bx[s] = pixels16<BF>(px);
+      }
+      f32x16 acc[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        f32x16 c = {};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          c = mfma<BF>(op(s_tab, LpLds<BF>::kFwd, mt, s, lane), bx[s], c);
+          if constexpr (BF) c = mfma<BF>(op(s_tab, LpLds<BF>::kFwdLo, mt, s, lane), bx[s], c);
+        }
+        acc[mt] = c;
+      }
+
+      // ---- public stores; keep the stored 16-bit values
+      uint32_t bits[2][16];
+      static_for<0, 2>([&](auto mtc) {
+        constexpr int mt = decltype(mtc)::value;
+        static_for<0, 16>([&](auto rc) {
+          constexpr int r = decltype(rc)::value;
+          constexpr int n0 = 32 * mt + 8 * (r >> 2) + (r & 3), n1 = n0 + 4;
+          const CoefSlot c0 = coef_slot(mask, n0), c1 = coef_slot(mask, n1);
+          const uint32_t priv = h ? c1.priv : c0.priv, rank = h ? c1.rank : c0.rank;
+          const uint32_t b = to16<BF>(acc[mt][r]);
+          bits[mt][r] = b;
+          if (bv && !priv) pub_tile[rank * ntb + jb] = (uint16_t)b;
+        });
+      });
+
+      // ---- inverse-transform operands: exchange lane halves so lane half h
+      // holds coefficients 16 s + 8 h + e (e = 0..7) of its block
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(bits[mt][8 * sl + e], bits[mt][8 * sl + 4 + e], false, false);
+            bits[mt][8 * sl + e] = sw[0];
+            bits[mt][8 * sl + 4 + e] = sw[1];
+          }
+      uint4 chi[4], clo[4];
+      static_for<0, 4>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        uint32_t hi16[8], lo16[8];
+        static_for<0, 8>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          constexpr int n0 = 16 * s + e, n1 = n0 + 8;
+          const CoefSlot c0 = coef_slot(mask, n0), c1 = coef_slot(mask, n1);
+          const uint32_t priv = h ? c1.priv : c0.priv, rank = h ? c1.rank : c0.rank;
+          hi16[e] = bits[s / 2][8 * (s & 1) + e];
+          lo16[e] = 0u;
+          if ((c0.priv | c1.priv) && priv) {
+            const int32_t q = bv ? (int32_t) * reinterpret_cast<const int16_t *>(lp + 2u * (rank * ntb + jb)) : 0;
+            split_int<BF>(q, hi16[e], lo16[e]);
+          }
+        });
+        chi[s] = make_uint4(hi16[0] | (hi16[1] << 16), hi16[2] | (hi16[3] << 16), hi16[4] | (hi16[5] << 16),
+                            hi16[6] | (hi16[7] << 16));
+        clo[s] = make_uint4(lo16[0] | (lo16[1] << 16), lo16[2] | (lo16[3] << 16), lo16[4] | (lo16[5] << 16),
+                            lo16[6] | (lo16[7] << 16));
+      });
+
+      // ---- reconstruction and residual plane
+      f32x16 y[2];
+      lp_idct<BF>(s_tab, lane, chi, clo, y);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const size_t off = borg + (size_t)(4 * mt + q4) * g.W + 4u * h;
+          const uint32_t xw = bv ? *reinterpret_cast<const uint32_t *>(g.pix + off) : 0u;
+          uint32_t rw = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int rec = (int)__builtin_amdgcn_fmed3f(__builtin_rintf(y[mt][4 * q4 + e]), 0.0f, 255.0f);
+            const int d = (int)((xw >> (8 * e)) & 0xffu) - rec;
+            rflag |= (d < -128 || d > 127) ? 1u : 0u;
+            rw |= ((uint32_t)d & 0xffu) << (8 * e);
+          }
+          if (bv) *reinterpret_cast<uint32_t *>(a.resid + off) = rw;
+        }
+    }
+
+    // ---- private bytes: AES-CTR and coalesced stores
+    wave_lds_sync();
+    tile_ctr_store(lp, a.priv + b0 * g.npriv * 2u, 2u * g.npriv * ntb, lane, s_aes, a.aes.enabled, a.aes.ctr_hi,
+                   a.aes.ctr_lo, b0 * g.npriv / 8u);
+    wave_lds_sync();
+  }
+  if (__ballot(rflag != 0u) != 0ull && lane == 0 && a.status) atomicOr(a.status, SF_STATUS_RESIDUAL_RANGE);
+}
+
+template <bool BF>
+__global__ __launch_bounds__(kThreads) void defrag_lp_kernel(LpDefragArgs a) {
+  __shared__ AesLds s_aes;
+  __shared__ LpLds<BF> s_tab;
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
+  load_lp_tables<BF>(s_tab, a.tables, threadIdx.x);
+  __syncthreads();
+  uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
+  const TileGeom &g = a.g;
+  const uint64_t mask = opaque_u64(g.mask);
+  const uint32_t h = (uint32_t)lane >> 5, jl = (uint32_t)lane & 31u;
+  const uint32_t stride = gridDim.x * kWaves;
+
+  for (uint32_t t = blockIdx.x * kWaves + wave; t < g.ntiles; t += stride) {
+    const uint64_t b0 = (uint64_t)t * 64u;
+    const uint32_t ntb = (uint32_t)min<uint64_t>(64u, g.nb - b0);
+    tile_ctr_load(lp, a.priv + b0 * g.npriv * 2u, 2u * g.npriv * ntb, lane, s_aes, a.aes.enabled, a.aes.ctr_hi,
+                  a.aes.ctr_lo, b0 * g.npriv / 8u);
+    wave_lds_sync();
+    const uint16_t *pub_tile = a.pub + b0 * g.npub;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const uint32_t jb = 32u * nt + jl;
+      const bool bv = jb < ntb;
+      const uint32_t borg = bv ? block_origin(g, (uint32_t)b0 + jb) : 0u;
+      uint4 chi[4], clo[4];
+      static_for<0, 4>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        uint32_t hi16[8], lo16[8];
+        static_for<0, 8>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          constexpr int n0 = 16 * s + e, n1 = n0 + 8;
+          const CoefSlot c0 = coef_slot(mask, n0), c1 = coef_slot(mask, n1);
+          const uint32_t priv = h ? c1.priv : c0.priv, rank = h ? c1.rank : c0.rank;
+          lo16[e] = 0u;
+          if (priv) {
+            const int32_t q = bv ? (int32_t) * reinterpret_cast<const int16_t *>(lp + 2u * (rank * ntb + jb)) : 0;
+            split_int<BF>(q, hi16[e], lo16[e]);
+          } else {
+            hi16[e] = bv ? (uint32_t)pub_tile[rank * ntb + jb] : 0u;
+          }
+        });
+        chi[s] = make_uint4(hi16[0] | (hi16[1] << 16), hi16[2] | (hi16[3] << 16), hi16[4] | (hi16[5] << 16),
+                            hi16[6] | (hi16[7] << 16));
+        clo[s] = make_uint4(lo16[0] | (lo16[1] << 16), lo16[2] | (lo16[3] << 16), lo16[4] | (lo16[5] << 16),
+                            lo16[6] | (lo16[7] << 16));
+      });
+      f32x16 y[2];
+      lp_idct<BF>(s_tab, lane, chi, clo, y);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const size_t off = borg + (size_t)(4 * mt + q4) * g.W + 4u * h;
+          const uint32_t rw = bv ? *reinterpret_cast<const uint32_t *>(a.resid + off) : 0u;
+          uint32_t ow = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int rec = (int)__builtin_amdgcn_fmed3f(__builtin_rintf(y[mt][4 * q4 + e]), 0.0f, 255.0f);
+            const int v = rec + (int)(int8_t)((rw >> (8 * e)) & 0xffu);
+            ow |= ((uint32_t)v & 0xffu) << (8 * e);
+          }
+          if (bv) *reinterpret_cast<uint32_t *>(a.pix_out + off) = ow;
+        }
+    }
+    wave_lds_sync();
+  }
+}
+
+uint32_t lds_priv_bytes(const Geom &g) { return (2u * g.npriv * 64u + 15u) & ~15u; }
+
+int grid_for(const DeviceState &ds, const void *kernel, size_t lds, uint32_t ntiles) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const uint32_t need = (ntiles + kWaves - 1) / kWaves;
+  const uint32_t cap = (uint32_t)ds.num_cu * (uint32_t)per_cu;
+  return (int)(need < cap ? need : cap);
+}
+
+template <bool BF>
+int lds_fits(const DeviceState &ds, size_t dynamic) {
+  const size_t total = sizeof(AesLds) + sizeof(LpLds<BF>) + dynamic;
+  if (total > ds.max_lds_per_block)
+    return fail(SF_ENOTSUP, "selection needs more LDS per workgroup than the device offers in this form");
+  return SF_OK;
+}
+
+template <bool BF>
+int launch_frag(const DeviceState &ds, const LpFragArgs &a, size_t lds, hipStream_t stream) {
+  if (int rc = lds_fits<BF>(ds, lds)) return rc;
+  const int grid = grid_for(ds, (const void *)&frag_lp_kernel<BF>, lds, a.g.ntiles);
+  hipLaunchKernelGGL(frag_lp_kernel<BF>, dim3(grid), dim3(kThreads), lds, stream, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SF_OK : hip_fail(e, "frag_lp kernel launch");
+}
+
+template <bool BF>
+int launch_defrag(const DeviceState &ds, const LpDefragArgs &a, size_t lds, hipStream_t stream) {
+  if (int rc = lds_fits<BF>(ds, lds)) return rc;
+  const int grid = grid_for(ds, (const void *)&defrag_lp_kernel<BF>, lds, a.g.ntiles);
+  hipLaunchKernelGGL(defrag_lp_kernel<BF>, dim3(grid), dim3(kThreads), lds, stream, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SF_OK : hip_fail(e, "defrag_lp kernel launch");
+}
+
+}  // namespace
+
+int launch_frag_lp(const DeviceState &ds, const Geom &g, const uint8_t *pix, void *pub, uint8_t *priv,
+                   int8_t *residual, const AesArgs &aes, uint32_t *status, hipStream_t stream) {
+  LpFragArgs a;
+  a.g = tile_geom(g, pix);
+  a.pub = (uint16_t *)pub;
+  a.priv = priv;
+  a.resid = residual;
+  a.status = status;
+  a.q2 = ds.d_q2;
+  a.tables = ds.d_lp;
+  a.aes_t0 = ds.d_aes_t0;
+  a.aes = aes;
+  a.lds_priv_bytes = lds_priv_bytes(g);
+  memset(a.plist, 0, sizeof(a.plist));
+  int i = 0;
+  static constexpr ZigZag zz{};
+  for (int z = 0; z < 64; ++z)
+    if ((g.mask >> z) & 1u) {
+      a.plist[i >> 2] |= (uint32_t)zz.nat[z] << (8 * (i & 3));
+      ++i;
+    }
+  const size_t lds = (size_t)kWaves * a.lds_priv_bytes;
+  return g.precision == SF_BF16 ? launch_frag<true>(ds, a, lds, stream) : launch_frag<false>(ds, a, lds, stream);
+}
+
+int launch_defrag_lp(const DeviceState &ds, const Geom &g, const void *pub, const uint8_t *priv,
+                     const int8_t *residual, const AesArgs &aes, uint8_t *pix, uint32_t *status,
+                     hipStream_t stream) {
+  LpDefragArgs a;
+  a.g = tile_geom(g, nullptr);
+  a.pub = (const uint16_t *)pub;
+  a.priv = priv;
+  a.resid = residual;
+  a.pix_out = pix;
+  a.status = status;
+  a.tables = ds.d_lp;
+  a.aes_t0 = ds.d_aes_t0;
+  a.aes = aes;
+  a.lds_priv_bytes = lds_priv_bytes(g);
+  const size_t lds = (size_t)kWaves * a.lds_priv_bytes;
+  return g.precision == SF_BF16 ? launch_defrag<true>(ds, a, lds, stream)
+                                : launch_defrag<false>(ds, a, lds, stream);
 }
 
 }  // namespace sf

@@ -46,6 +46,15 @@ struct ZigZag {
 };
 inline constexpr ZigZag kZigZag{};
 
+// Inverse table: natural index 8u + v -> zigzag position.
+struct ZigZagInv {
+  int pos[64];
+  constexpr ZigZagInv() : pos{} {
+    for (int z = 0; z < 64; ++z) pos[kZigZag.nat[z]] = z;
+  }
+};
+inline constexpr ZigZagInv kZigZagInv{};
+
 // ---------------------------------------------------------------------------
 // Orthonormal 8-point DCT-II constants (host computes them; see tables.cpp):
 //   s0 = 1/sqrt(8), a = cos(pi/8)/2, b = cos(3pi/8)/2, cK = cos(K pi/16)/2.

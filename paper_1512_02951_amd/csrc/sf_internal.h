@@ -11,6 +11,12 @@
 
 namespace sf {
 
+// MFMA operand tables: f16 forward, f16 inverse, bf16 forward hi/lo, bf16
+// inverse hi/lo; each 2 M-tiles x 4 K-steps x 64 lanes x 4 words.
+constexpr int kLpTables = 6;
+constexpr int kLpTableWords = 2 * 4 * 64 * 4;
+void build_lp_tables(const double *basis, uint32_t (*lp)[kLpTableWords]);
+
 // Host-generated constant tables (tables.cpp), independent of any device.
 struct HostTables {
   uint32_t aes_t0[256];                  // T0[x] = (2S, S, S, 3S) bytes, little-endian word
@@ -20,6 +26,9 @@ struct HostTables {
   float cert_m[64];                      // max_p |B[n][p]| (rounded up), per natural index
   float cert_e[64];                      // 255 * sum_p |Bq/2^20 - B| (rounded up)
   DctK dct;                              // butterfly constants
+  double basis[64 * 64];                 // B[n][p] (long double rounded to double)
+  // MFMA operand tables of the reduced-precision form, per-lane order (lp.hip)
+  uint32_t lp[kLpTables][kLpTableWords];
 };
 const HostTables &host_tables();
 void aes_expand_key(const uint8_t key[16], uint32_t rk[44]);
@@ -34,6 +43,8 @@ struct DeviceState {
   int num_cu = 0;
   uint32_t *d_aes_t0 = nullptr;
   uint32_t *d_q2 = nullptr;
+  uint32_t *d_lp = nullptr;  // kLpTables x kLpTableWords
+  size_t max_lds_per_block = 65536;
 };
 // Lazily initialise the current device; returns SF_OK or an error code.
 int device_state(DeviceState **out);

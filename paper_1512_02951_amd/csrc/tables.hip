@@ -67,6 +67,7 @@ void build_dct(HostTables &t) {
       for (int y = 0; y < 8; ++y)
         for (int x = 0; x < 8; ++x) {
           const long double bv = dct_entry(u, y) * dct_entry(v, x);
+          t.basis[n * 64 + 8 * y + x] = (double)bv;
           const long double scaled = ldexpl(bv, 20);
           const int32_t q = (int32_t)llrintl(scaled);  // default rounding: to nearest, ties to even
           qi[8 * y + x] = q;
@@ -105,6 +106,7 @@ const HostTables &host_tables() {
   std::call_once(g_once, [] {
     build_aes(g_tables);
     build_dct(g_tables);
+    build_lp_tables(g_tables.basis, g_tables.lp);
   });
   return g_tables;
 }

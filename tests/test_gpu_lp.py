@@ -1,0 +1,138 @@
+"""GPU parity of the reduced-precision form (fp16 / bf16 MFMA transforms with
+an int8 residual plane) against the CPU oracle, through the C ABI.
+
+Bars: private integers and ciphertext bit-exact; public coefficients within
+2e-3 of the FP64 oracle, normwise per block relative to the block's pixel
+norm (the stored 16-bit values included); reconstructed pixels bit-exact
+through the residual plane; residuals within int8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+sf = pytest.importorskip("paper_1512_02951_amd")
+
+pytestmark = pytest.mark.gpu
+
+TOL_LP = 2e-3
+DT = {"fp16": np.float16, "bf16": None}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    assert sf.lib().sf_init() == 0, sf.lib().sf_last_error()
+
+
+def _public_f64(t: torch.Tensor) -> np.ndarray:
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def _check(x, mask, prec, key=None, ctr0=None, label=""):
+    print("case:", label, prec, x.shape, hex(mask), flush=True)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    fr = sf.frag_image(xd, mask, key, ctr0, precision=prec, status=status)
+    y = sf.defrag_image(fr, key, ctr0, status=status)
+    torch.cuda.synchronize()
+    ref = oracle.frag(x, mask, key, ctr0)
+    nb, npriv = ref["nb"], ref["npriv"]
+    npub = 64 - npriv
+    got = fr.private.cpu().numpy()[: 2 * nb * npriv]
+    if key is None:
+        assert np.array_equal(got.view("<i2"), ref["private"]), "private integers differ"
+    else:
+        assert np.array_equal(got, ref["cipher"]), "ciphertext differs"
+    if npub:
+        pub = oracle.tile_unpack(_public_f64(fr.public[: nb * npub]), nb, npub)
+        pub_ref = oracle.tile_unpack(ref["public"], nb, npub)
+        nrm = np.linalg.norm(oracle.blocks_of(x).astype(np.float64), axis=1)
+        err = np.linalg.norm(pub - pub_ref, axis=1)
+        zero = nrm == 0
+        assert np.all(err[zero] == 0), "all-zero block not exactly zero"
+        rel = err[~zero] / nrm[~zero]
+        assert rel.size == 0 or rel.max() <= TOL_LP, "public rel err %g" % rel.max()
+        print("  public max normwise rel err %.3e" % (rel.max() if rel.size else 0.0), flush=True)
+    r = fr.residual.cpu().numpy()
+    print("  residual nonzero fraction %.3e, max |r| %d" % (np.count_nonzero(r) / r.size, np.abs(r.astype(int)).max()),
+          flush=True)
+    assert int(status.item()) == 0, "status %d" % status.item()
+    assert torch.equal(y.cpu(), torch.from_numpy(x)), "round trip differs"
+    return fr, ref
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("shape,k", [((1, 64, 64), 9), ((3, 24, 40), 5), ((1, 8, 8), 0), ((2, 136, 264), 9),
+                                     ((1, 512, 512), 9), ((1, 64, 64), 63)])
+def test_lp_shapes(prec, shape, k):
+    C, H, W = shape
+    x = synth.image(H, W, C, 3, 1).numpy()
+    _check(x, sf.prefix_mask(k), prec, synth.aes_key(3), synth.ctr0(3, 1), "lp")
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("mask", [0b111110, 0x8000000000000001, (1 << 64) - 1])
+def test_lp_runtime_masks_and_clear_private(prec, mask):
+    rng = np.random.default_rng(2)
+    x = rng.integers(0, 256, size=(1, 64, 128), dtype=np.uint8)
+    x[0, :8, :8] = 255
+    x[0, 8:16, :8] = 0
+    _check(x, mask, prec, None, None, "lp runtime mask")
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_lp_workload3_full_size(prec):
+    """16 grayscale 8192x8192 images, k = 9: every round trip exact on the GPU,
+    2048 sampled blocks per image compared with the oracle."""
+    mask = sf.prefix_mask(9)
+    key = synth.aes_key(3)
+    H = W = 8192
+    nb = H * W // 64
+    npub, npriv = 54, 10
+    x = torch.empty((1, H, W), dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    worst = 0.0
+    rng = np.random.default_rng(33)
+    for img in range(16):
+        print("case: workload 3 image", img, prec, flush=True)
+        synth.image(H, W, 1, 3, img, device="cuda", out=x)
+        c0 = synth.ctr0(3, img)
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        fr = sf.frag_image(x, mask, key, c0, precision=prec, status=status)
+        sf.defrag_image(fr, key, c0, out=y, status=status)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        assert torch.equal(x, y), "image %d round trip differs" % img
+        # sampled blocks: oracle on a strip made of those blocks
+        blocks = np.sort(rng.choice(nb, 2048, replace=False))
+        xb = x[0].view(H // 8, 8, W // 8, 8).permute(0, 2, 1, 3).reshape(nb, 64)[torch.from_numpy(blocks).cuda()]
+        xb = xb.cpu().numpy()
+        strip = xb.reshape(-1, 8, 8).transpose(1, 0, 2).reshape(8, -1)[None]
+        ref = oracle.frag(strip, mask)
+        ref_priv = oracle.tile_unpack(ref["private"], blocks.size, npriv)
+        ref_pub = oracle.tile_unpack(ref["public"], blocks.size, npub)
+        pub_all = fr.public
+        priv_all = fr.private.cpu().numpy()
+        # decrypt the sampled private values with the oracle keystream
+        for j in range(npriv):
+            byte = 2 * oracle.tile_offsets(nb, npriv, blocks, j)
+            ks = oracle.ctr_keystream(key, c0, byte // 16)
+            k0 = ks[np.arange(byte.size), byte % 16]
+            k1 = ks[np.arange(byte.size), byte % 16 + 1]
+            plain = (priv_all[byte] ^ k0).astype(np.uint16) | ((priv_all[byte + 1] ^ k1).astype(np.uint16) << 8)
+            assert np.array_equal(plain.view(np.int16), ref_priv[:, j]), "private coefficient %d differs" % j
+        idx = oracle.tile_offsets(nb, npub, np.repeat(blocks, npub), np.tile(np.arange(npub), blocks.size))
+        got = _public_f64(pub_all[torch.from_numpy(idx).cuda()]).reshape(blocks.size, npub)
+        nrm = np.linalg.norm(xb.astype(np.float64), axis=1)
+        err = np.linalg.norm(got - ref_pub, axis=1)
+        ok = nrm > 0
+        assert np.all(err[~ok] == 0)
+        rel = err[ok] / nrm[ok]
+        worst = max(worst, float(rel.max()))
+        assert rel.max() <= TOL_LP
+        del fr
+    print("workload 3 %s: worst sampled public normwise rel err %.3e" % (prec, worst), flush=True)

@@ -85,3 +85,14 @@ def test_ctr_is_an_involution_and_errors_stay_local():
     bad[123] ^= 0x10
     diff = oracle.ctr_xor(key, ctr0, bad) ^ pt
     assert np.count_nonzero(diff) == 1 and diff[123] == 0x10
+
+
+def test_ctr_keystream_blocks_match_published_vector():
+    rows = golden("sp800_38a_ctr_aes128.txt")
+    key = bytes.fromhex([r for r in rows if r[0] == "key"][0][1])
+    ctr0 = bytes.fromhex([r for r in rows if r[0] == "ctr0"][0][1])
+    blocks = [r for r in rows if r[0] == "block"]
+    ks = oracle.ctr_keystream(key, ctr0, [3, 0, 2, 1])
+    for row, i in zip(ks, [3, 0, 2, 1]):
+        pt, ct = bytes.fromhex(blocks[i][1]), bytes.fromhex(blocks[i][2])
+        assert bytes(a ^ b for a, b in zip(row.tobytes(), pt)) == ct

@@ -120,3 +120,11 @@ def test_different_nonce_changes_ciphertext():
     a = oracle.frag(pix, oracle.prefix_mask(5), key, synth.ctr0(1, 0))["cipher"]
     b = oracle.frag(pix, oracle.prefix_mask(5), key, synth.ctr0(1, 1))["cipher"]
     assert not np.array_equal(a, b)
+
+
+def test_vector_tile_offsets_match_scalar_definition():
+    for nb, P in ((70, 2), (64, 5), (1, 3), (200, 58)):
+        b = np.repeat(np.arange(nb), P)
+        j = np.tile(np.arange(P), nb)
+        vec = oracle.tile_offsets(nb, P, b, j)
+        assert np.array_equal(vec, [oracle.tile_offset(nb, P, int(x), int(y)) for x, y in zip(b, j)])
