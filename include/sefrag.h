@@ -170,6 +170,61 @@ int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_pri
 int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *d_in, uint8_t *d_out,
                     size_t nbytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Batched form: many images of uneven sizes and selections (plain FP32
+ * form) in one persistent kernel per direction.  Images are independent
+ * pieces of data (the report's arbitrary data chunked into matrices and
+ * processed block by block, Sec. 6.9.3; a series of images, Sec. 6.5.1),
+ * each with its own counter block (a different IV per input, Sec. 6.10.6).
+ * ------------------------------------------------------------------- */
+
+/* One image of a batch.  Host struct; the pointers are device pointers
+ * owned by the caller, with the layouts and alignments of frag_image. */
+typedef struct sf_batch_item {
+  uint32_t height, width, channels; /* as in sf_desc (multiples of 8)             */
+  uint32_t exc_per_tile;            /* exception slots per tile (see sf_exceptions) */
+  uint64_t private_mask;            /* as in sf_desc                                */
+  const uint8_t *d_pixels;          /* frag input image                             */
+  uint8_t *d_restored;              /* defrag output image                          */
+  float *d_public;                  /* FP32 public fragment                         */
+  uint8_t *d_private;               /* private fragment                             */
+  void *d_exc;                      /* exception buffer, or NULL if not needed      */
+  uint8_t ctr0[16];                 /* this image's initial counter block           */
+} sf_batch_item;
+
+/* Launch shape of a batch run: consecutive 64-block tiles a wavefront takes
+ * per grab of the work queue, and workgroups (of 4 wavefronts) per compute
+ * unit (0 = as many as fit).  NULL tuning = {2, 0}. */
+typedef struct sf_batch_tuning {
+  uint32_t tiles_per_grab;
+  uint32_t workgroups_per_cu;
+  uint32_t reserved[2];
+} sf_batch_tuning;
+
+/* Device workspace bytes for a plan of n_items images. */
+size_t sf_batch_workspace_bytes(uint32_t n_items);
+
+/* Validates the items, writes their descriptors, tile counts and the AES key
+ * (key = 16 host bytes, or NULL to leave private integers in clear) into
+ * d_workspace, and scans the counts on the device.  Synchronises `stream`
+ * before returning (the host item array may be released afterwards).  Not
+ * capturable into a graph; the run calls below are.  Returns SF_OK,
+ * SF_EINVAL (bad item, with its index in sf_last_error), SF_ESHAPE,
+ * SF_ERANGE (workspace too small) or SF_EHIP. */
+int sf_batch_plan(const sf_batch_item *items, uint32_t n_items, const uint8_t *key, void *d_workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* Fragment / defragment every image of the planned batch: a reset of the
+ * work counter plus one persistent kernel, both on `stream`. */
+int sf_frag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream);
+int sf_defrag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream);
+
+/* Autotuner: times frag + defrag of the planned batch for tiles_per_grab in
+ * {1,2,4,8,16} x workgroups_per_cu in {1,2,3} (one warm pass, two timed
+ * round trips each) and returns the fastest; *best_ms = its round-trip time.
+ * Runs the batch many times (outputs are rewritten with identical values). */
+int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *best_ms, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

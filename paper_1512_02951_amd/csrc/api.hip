@@ -226,6 +226,49 @@ int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_pri
   return rc;
 }
 
+size_t sf_batch_workspace_bytes(uint32_t n_items) { return batch_workspace_bytes(n_items); }
+
+int sf_batch_plan(const sf_batch_item *items, uint32_t n_items, const uint8_t *key, void *d_workspace,
+                  size_t workspace_bytes, void *stream) {
+  if (!items || n_items == 0) return fail(SF_EINVAL, "empty batch");
+  if (!d_workspace) return fail(SF_EINVAL, "NULL workspace");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  rc = batch_plan(*ds, items, n_items, key, d_workspace, workspace_bytes, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+static int batch_run_api(const void *d_workspace, int which, const sf_batch_tuning *tuning, uint32_t *d_status,
+                         void *stream) {
+  if (!d_workspace) return fail(SF_EINVAL, "NULL workspace");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  rc = batch_run(*ds, d_workspace, which, tuning, d_status, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_frag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream) {
+  return batch_run_api(d_workspace, 0, tuning, d_status, stream);
+}
+
+int sf_defrag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream) {
+  return batch_run_api(d_workspace, 1, tuning, d_status, stream);
+}
+
+int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *best_ms, void *stream) {
+  if (!d_workspace || !best) return fail(SF_EINVAL, "NULL argument");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  rc = batch_autotune(*ds, d_workspace, best, best_ms, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
 int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *d_in, uint8_t *d_out,
                     size_t nbytes, void *stream) {
   if (!aes) return fail(SF_EINVAL, "aes is NULL");

@@ -1,0 +1,397 @@
+// Batched form: many images of uneven sizes and selections in one persistent
+// kernel per direction.
+//
+//   plan (host, once):  validate the items, write per-image descriptors,
+//                       per-image tile counts and the AES key into the
+//                       caller's device workspace; a one-workgroup device
+//                       scan (wave prefix sums) turns the counts into tile
+//                       offsets.
+//   run  (graph-safe):  a tiny kernel clears the work counter, then a
+//                       persistent grid of waves grabs `tiles_per_grab`
+//                       consecutive global tiles at a time from an atomic
+//                       queue, finds each tile's image by binary search over
+//                       the offsets, and runs the same per-tile body as the
+//                       single-image kernels (plain_tile.h) with that image's
+//                       geometry, selection, fragments and counter block.
+//
+// The tuner times candidate (tiles_per_grab, workgroups per CU) pairs on the
+// planned batch and reports the fastest.
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "plain_tile.h"
+
+namespace sf {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+struct BatchDesc {
+  TileGeom g;
+  uint8_t *out;
+  float *pub;
+  uint8_t *priv;
+  ExcSlots exc;
+  uint64_t ctr_hi, ctr_lo;
+};
+
+// Device workspace layout (all offsets multiples of 16 bytes).
+struct BatchHeader {
+  uint32_t n;            // images
+  uint32_t enc;          // AES enabled
+  uint32_t total_tiles;  // filled by the scan
+  uint32_t max_npriv;
+  uint32_t queue[4];     // work counters (frag, defrag)
+  AesKey key;
+};
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15u) & ~(size_t)15u; }
+
+struct WsLayout {
+  size_t desc, counts, offsets, total;
+};
+__host__ __device__ inline WsLayout ws_layout(uint32_t n) {
+  WsLayout L;
+  L.desc = align16(sizeof(BatchHeader));
+  L.counts = L.desc + align16(sizeof(BatchDesc) * (size_t)n);
+  L.offsets = L.counts + align16(4u * (size_t)n);
+  L.total = L.offsets + align16(4u * ((size_t)n + 1u));
+  return L;
+}
+
+// Exclusive scan of n tile counts -> n + 1 offsets (offsets[n] = total), one
+// workgroup of 1024 threads, chunks of 1024 with a running carry.
+__global__ __launch_bounds__(1024) void batch_scan_kernel(uint8_t *ws, uint32_t n) {
+  const WsLayout L = ws_layout(n);
+  const uint32_t *counts = reinterpret_cast<const uint32_t *>(ws + L.counts);
+  uint32_t *offs = reinterpret_cast<uint32_t *>(ws + L.offsets);
+  __shared__ uint32_t wave_sums[16];
+  __shared__ uint32_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n; base += 1024) {
+    const uint32_t i = base + tid;
+    const uint32_t v = i < n ? counts[i] : 0u;
+    uint32_t wtotal;
+    const uint32_t excl = wave_exclusive_scan(v, lane, wtotal);
+    if (lane == 0) wave_sums[wave] = wtotal;
+    __syncthreads();
+    uint32_t before = carry;
+    for (int w = 0; w < wave; ++w) before += wave_sums[w];
+    if (i < n) offs[i] = before + excl;
+    __syncthreads();
+    if (tid == 1023) carry = before + excl + v;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    offs[n] = carry;
+    reinterpret_cast<BatchHeader *>(ws)->total_tiles = carry;
+  }
+}
+
+__global__ void batch_reset_kernel(uint8_t *ws, int which) { reinterpret_cast<BatchHeader *>(ws)->queue[which] = 0u; }
+
+// Descriptor words through the scalar cache (the table is read-only while a
+// batch kernel runs), so the image's geometry and pointers sit in SGPRs.
+__device__ __forceinline__ BatchDesc load_desc(const BatchDesc *p) {
+  static_assert(sizeof(BatchDesc) % 4 == 0, "descriptor must be whole words");
+  constexpr int kWords = (int)(sizeof(BatchDesc) / 4);
+  uint32_t w[kWords];
+  const cu32_ptr src = as_const(reinterpret_cast<const uint32_t *>(p));
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) w[i] = src[i];
+  BatchDesc d;
+  __builtin_memcpy(&d, w, sizeof(d));
+  return d;
+}
+
+// Image holding global tile gt: the last i with offsets[i] <= gt.
+__device__ __forceinline__ uint32_t find_image(const uint32_t *offs, uint32_t n, uint32_t gt) {
+  uint32_t lo = 0, hi = n;  // offs[lo] <= gt < offs[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (offs[mid] <= gt) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Runs body(tile, desc) for every tile of the batch, grabbing
+// tiles_per_grab consecutive tiles per atomic.
+template <class Body>
+__device__ __forceinline__ void batch_loop(uint8_t *ws, uint32_t n, int which, uint32_t tiles_per_grab, int lane,
+                                           Body &&body) {
+  const WsLayout L = ws_layout(n);
+  BatchHeader *hd = reinterpret_cast<BatchHeader *>(ws);
+  const BatchDesc *descs = reinterpret_cast<const BatchDesc *>(ws + L.desc);
+  const uint32_t *offs = reinterpret_cast<const uint32_t *>(ws + L.offsets);
+  const uint32_t total = hd->total_tiles;
+  for (;;) {
+    uint32_t w = 0;
+    if (lane == 0) w = atomicAdd(&hd->queue[which], tiles_per_grab);
+    w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
+    if (w >= total) break;
+    const uint32_t end = min(w + tiles_per_grab, total);
+    uint32_t img = find_image(offs, n, w);
+    for (uint32_t gt = w; gt < end; ++gt) {
+      while (offs[img + 1] <= gt) ++img;
+      img = __builtin_amdgcn_readfirstlane(img);
+      body(gt - offs[img], load_desc(descs + img));
+    }
+  }
+}
+
+struct BatchArgs {
+  uint8_t *ws;
+  uint32_t n;
+  uint32_t tiles_per_grab;
+  uint32_t lds_priv_bytes;
+  uint32_t *status;
+  const uint32_t *aes_t0;
+  const uint32_t *q2;
+  float cert_thr;
+  DctK K;
+};
+
+template <class F>
+__device__ __forceinline__ void dispatch_mask(uint64_t mask, F &&f) {
+  switch (mask) {
+    case (1ull << 2) - 1: f(MaskPrefix<2>{}); break;
+    case (1ull << 3) - 1: f(MaskPrefix<3>{}); break;
+    case (1ull << 6) - 1: f(MaskPrefix<6>{}); break;
+    case (1ull << 10) - 1: f(MaskPrefix<10>{}); break;
+    default: f(MaskRuntime{}); break;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void frag_batch_kernel(BatchArgs a) {
+  __shared__ AesLds s_aes;
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(a.ws);
+  const uint32_t enc = hd->enc;
+  if (enc) aes_load_tables(s_aes, a.aes_t0, hd->key, threadIdx.x, kThreads);
+  __syncthreads();
+  uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
+  batch_loop(a.ws, a.n, 0, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) {
+    FragOut o;
+    o.pub = d.pub;
+    o.priv = d.priv;
+    o.exc = d.exc;
+    o.status = a.status;
+    o.q2 = a.q2;
+    o.cert_thr = a.cert_thr;
+    const TileLane L = tile_lane(d.g, t, lane);
+    uint32_t xs[16];
+    load_block(d.g, L, xs);
+    dispatch_mask(d.g.mask, [&](auto mp) {
+      frag_tile<decltype(mp)>(d.g, o, t, L, xs, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K);
+    });
+  });
+}
+
+__global__ __launch_bounds__(kThreads) void defrag_batch_kernel(BatchArgs a) {
+  __shared__ AesLds s_aes;
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(a.ws);
+  const uint32_t enc = hd->enc;
+  if (enc) aes_load_tables(s_aes, a.aes_t0, hd->key, threadIdx.x, kThreads);
+  __syncthreads();
+  uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
+  batch_loop(a.ws, a.n, 1, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) {
+    DefragIn in;
+    in.pix_out = d.out;
+    in.pub = d.pub;
+    in.priv = d.priv;
+    in.exc = d.exc;
+    const TileLane L = tile_lane(d.g, t, lane);
+    dispatch_mask(d.g.mask, [&](auto mp) {
+      defrag_tile<decltype(mp)>(d.g, in, t, L, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K);
+    });
+  });
+}
+
+// Host copy of the plan's facts needed at launch time (kept per workspace).
+struct PlanInfo {
+  const void *ws = nullptr;
+  uint32_t n = 0, max_npriv = 0;
+  uint64_t total_tiles = 0;
+};
+std::vector<PlanInfo> g_plans;  // guarded by g_plan_mu
+std::mutex g_plan_mu;
+
+int find_plan(const void *ws, PlanInfo *out) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (const PlanInfo &p : g_plans)
+    if (p.ws == ws) {
+      *out = p;
+      return SF_OK;
+    }
+  return fail(SF_EINVAL, "workspace has no batch plan (call sf_batch_plan first)");
+}
+
+int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_batch_tuning *tuning,
+                 uint32_t *status, hipStream_t stream) {
+  BatchArgs a;
+  a.ws = (uint8_t *)p.ws;
+  a.n = p.n;
+  a.tiles_per_grab = tuning && tuning->tiles_per_grab ? tuning->tiles_per_grab : 2u;
+  a.lds_priv_bytes = (2u * p.max_npriv * 64u + 15u) & ~15u;
+  a.status = status;
+  a.aes_t0 = ds.d_aes_t0;
+  a.q2 = ds.d_q2;
+  a.cert_thr = cert_threshold();
+  a.K = host_tables().dct;
+  if (a.tiles_per_grab > 1024) return fail(SF_ERANGE, "tiles_per_grab must be at most 1024");
+  const size_t lds = (size_t)kWaves * a.lds_priv_bytes;
+  const void *fn = which == 0 ? (const void *)frag_batch_kernel : (const void *)defrag_batch_kernel;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (tuning && tuning->workgroups_per_cu) per_cu = tuning->workgroups_per_cu < (uint32_t)per_cu ? (int)tuning->workgroups_per_cu : per_cu;
+  uint64_t need = (p.total_tiles + (uint64_t)kWaves * a.tiles_per_grab - 1) / ((uint64_t)kWaves * a.tiles_per_grab);
+  uint64_t grid = (uint64_t)ds.num_cu * (uint64_t)per_cu;
+  if (need < grid) grid = need;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.ws, which);
+  if (which == 0)
+    hipLaunchKernelGGL(frag_batch_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+  else
+    hipLaunchKernelGGL(defrag_batch_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SF_OK : hip_fail(e, "batch kernel launch");
+}
+
+}  // namespace
+
+size_t batch_workspace_bytes(uint32_t n) { return ws_layout(n).total; }
+
+int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, const uint8_t *key, void *d_ws,
+               size_t ws_bytes, hipStream_t stream) {
+  const WsLayout L = ws_layout(n);
+  if (ws_bytes < L.total) return fail(SF_ERANGE, "batch workspace too small (see sf_batch_workspace_bytes)");
+  if ((uintptr_t)d_ws & 15u) return fail(SF_EINVAL, "workspace must be 16-byte aligned");
+  std::vector<uint8_t> host(L.total, 0);
+  BatchHeader *hd = reinterpret_cast<BatchHeader *>(host.data());
+  BatchDesc *descs = reinterpret_cast<BatchDesc *>(host.data() + L.desc);
+  uint32_t *counts = reinterpret_cast<uint32_t *>(host.data() + L.counts);
+  hd->n = n;
+  hd->enc = key ? 1u : 0u;
+  if (key) aes_expand_key(key, hd->key.rk);
+  uint64_t total = 0;
+  uint32_t max_npriv = 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    const sf_batch_item &it = items[i];
+    sf_desc d;
+    d.height = it.height;
+    d.width = it.width;
+    d.channels = it.channels;
+    d.precision = SF_FP32;
+    d.private_mask = it.private_mask;
+    Geom g;
+    if (int rc = make_geom(&d, &g)) return fail(rc, "item " + std::to_string(i) + ": " + ::sf_last_error());
+    if (!it.d_pixels && !it.d_restored) return fail(SF_EINVAL, "item " + std::to_string(i) + ": no image buffer");
+    if (!it.d_private || (g.npub && !it.d_public))
+      return fail(SF_EINVAL, "item " + std::to_string(i) + ": NULL fragment pointer");
+    if (((uintptr_t)it.d_pixels | (uintptr_t)it.d_restored) & 7u || ((uintptr_t)it.d_public | (uintptr_t)it.d_private) & 15u)
+      return fail(SF_EINVAL, "item " + std::to_string(i) + ": misaligned buffer");
+    BatchDesc &bd = descs[i];
+    bd.g = tile_geom(g, it.d_pixels);
+    bd.out = it.d_restored;
+    bd.pub = it.d_public;
+    bd.priv = it.d_private;
+    sf_exceptions ex{it.d_exc, it.exc_per_tile};
+    bd.exc = ExcSlots{};
+    bd.exc.check = mask_needs_check(g.mask) ? 1u : 0u;
+    if (bd.exc.check) {
+      if (!it.d_exc || it.exc_per_tile == 0 || it.exc_per_tile > kMaxExcPerTile || ((uintptr_t)it.d_exc & 15u))
+        return fail(SF_EINVAL, "item " + std::to_string(i) + ": this selection needs an exception buffer");
+      bd.exc = exc_slots(g, &ex);
+    }
+    uint64_t hi = 0, lo = 0;
+    for (int b = 0; b < 8; ++b) hi = (hi << 8) | it.ctr0[b];
+    for (int b = 8; b < 16; ++b) lo = (lo << 8) | it.ctr0[b];
+    bd.ctr_hi = hi;
+    bd.ctr_lo = lo;
+    counts[i] = g.ntiles;
+    total += g.ntiles;
+    if (g.npriv > max_npriv) max_npriv = g.npriv;
+  }
+  if (total >= (1ull << 32)) return fail(SF_ERANGE, "batch holds too many tiles");
+  hd->max_npriv = max_npriv;
+  hipError_t e = hipMemcpyAsync(d_ws, host.data(), L.total, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch plan)");
+  hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(1024), 0, stream, (uint8_t *)d_ws, n);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch scan launch");
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize(batch plan)");
+  PlanInfo p;
+  p.ws = d_ws;
+  p.n = n;
+  p.max_npriv = max_npriv;
+  p.total_tiles = total;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (PlanInfo &q : g_plans)
+    if (q.ws == d_ws) {
+      q = p;
+      return SF_OK;
+    }
+  g_plans.push_back(p);
+  (void)ds;
+  return SF_OK;
+}
+
+int batch_run(const DeviceState &ds, const void *d_ws, int which, const sf_batch_tuning *tuning, uint32_t *status,
+              hipStream_t stream) {
+  PlanInfo p;
+  if (int rc = find_plan(d_ws, &p)) return rc;
+  return launch_batch(ds, p, which, tuning, status, stream);
+}
+
+int batch_autotune(const DeviceState &ds, const void *d_ws, sf_batch_tuning *best, float *best_ms,
+                   hipStream_t stream) {
+  PlanInfo p;
+  if (int rc = find_plan(d_ws, &p)) return rc;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SF_EHIP, "hipEventCreate failed");
+  static const uint32_t grabs[] = {1, 2, 4, 8, 16};
+  float best_t = 1e30f;
+  sf_batch_tuning best_c{2, 0, {0, 0}};
+  int rc = SF_OK;
+  for (uint32_t wpc = 1; wpc <= 3 && rc == SF_OK; ++wpc)
+    for (uint32_t gi = 0; gi < sizeof(grabs) / sizeof(grabs[0]) && rc == SF_OK; ++gi) {
+      sf_batch_tuning c{grabs[gi], wpc, {0, 0}};
+      // one untimed pass, then two timed round trips
+      for (int w = 0; w < 1 && rc == SF_OK; ++w) {
+        rc = launch_batch(ds, p, 0, &c, nullptr, stream);
+        if (rc == SF_OK) rc = launch_batch(ds, p, 1, &c, nullptr, stream);
+      }
+      (void)hipEventRecord(e0, stream);
+      for (int r = 0; r < 2 && rc == SF_OK; ++r) {
+        rc = launch_batch(ds, p, 0, &c, nullptr, stream);
+        if (rc == SF_OK) rc = launch_batch(ds, p, 1, &c, nullptr, stream);
+      }
+      (void)hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = fail(SF_EHIP, "hipEventSynchronize failed");
+      float ms = 0.0f;
+      if (rc == SF_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms / 2 < best_t) {
+        best_t = ms / 2;
+        best_c = c;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  *best = best_c;
+  if (best_ms) *best_ms = best_t;
+  return SF_OK;
+}
+
+}  // namespace sf

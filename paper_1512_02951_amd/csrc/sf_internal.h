@@ -92,6 +92,14 @@ int launch_frag_lp(const DeviceState &ds, const Geom &g, const uint8_t *pix, voi
 int launch_defrag_lp(const DeviceState &ds, const Geom &g, const void *pub, const uint8_t *priv,
                      const int8_t *residual, const AesArgs &aes, uint8_t *pix, uint32_t *status,
                      hipStream_t stream);
+// Batched form (batch.hip).
+size_t batch_workspace_bytes(uint32_t n);
+int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, const uint8_t *key, void *d_ws,
+               size_t ws_bytes, hipStream_t stream);
+int batch_run(const DeviceState &ds, const void *d_ws, int which, const sf_batch_tuning *tuning, uint32_t *status,
+              hipStream_t stream);
+int batch_autotune(const DeviceState &ds, const void *d_ws, sf_batch_tuning *best, float *best_ms,
+                   hipStream_t stream);
 int launch_ctr(const DeviceState &ds, const AesArgs &aes, uint64_t first_block, const uint8_t *in, uint8_t *out,
                size_t nbytes, hipStream_t stream);
 

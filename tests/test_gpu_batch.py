@@ -1,0 +1,167 @@
+"""GPU tests of the batched form: every image of a mixed batch gives exactly the
+fragments of the single-image path (itself checked against the oracle in
+test_gpu_plain.py), matches the oracle directly on sampled blocks, and
+restores bit-exactly; graph replays, the tuner and the 2000-image workload."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+sf = pytest.importorskip("paper_1512_02951_amd")
+from paper_1512_02951_amd.batch import Batch  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    assert sf.lib().sf_init() == 0, sf.lib().sf_last_error()
+
+
+def _mixed(n=24, seed=4):
+    rng = np.random.default_rng(seed)
+    imgs, masks, ctrs = [], [], []
+    for i in range(n):
+        H = int(8 * rng.integers(1, 40))
+        W = int(8 * rng.integers(1, 60))
+        C = int(rng.choice([1, 3]))
+        imgs.append(synth.image(H, W, C, 4, 1000 + i).cuda())
+        k = int(rng.choice([1, 2, 5, 9]))
+        masks.append(sf.prefix_mask(k) if i % 7 else int(rng.integers(1, 1 << 40)))
+        ctrs.append(synth.ctr0(4, 1000 + i))
+    return imgs, masks, ctrs
+
+
+def _check_against_single(b, imgs, masks, ctrs, key):
+    for i, (x, m, c0) in enumerate(zip(imgs, masks, ctrs)):
+        C, H, W = x.shape
+        fr = sf.Fragments(torch.empty_like(b.publics[i]), torch.empty_like(b.privates[i]),
+                          sf.ExceptionList(torch.zeros_like(b.excs[i]) if b.excs[i] is not None else None,
+                                           sf.DEFAULT_PER_TILE, (C, H, W)), None, (C, H, W), m, "fp32")
+        sf.frag_image(x, m, key, c0, out=fr)
+        torch.cuda.synchronize()
+        assert torch.equal(fr.private, b.privates[i]), "image %d private differs" % i
+        assert torch.equal(fr.public.view(torch.int32), b.publics[i].view(torch.int32)), "image %d public" % i
+        if b.excs[i] is not None:
+            ea = sf.ExceptionList(b.excs[i], sf.DEFAULT_PER_TILE, (C, H, W)).decode()
+            eb = fr.exceptions.decode()
+            assert np.array_equal(ea[2], eb[2])
+            assert sorted(zip(ea[0].tolist(), ea[1].tolist())) == sorted(zip(eb[0].tolist(), eb[1].tolist()))
+        assert torch.equal(b.restored[i], x), "image %d round trip" % i
+
+
+def test_mixed_batch_matches_single_image_path_and_oracle():
+    imgs, masks, ctrs = _mixed()
+    key = synth.aes_key(4)
+    b = Batch(imgs, masks, key, ctrs)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.frag(status=status)
+    b.defrag(status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    _check_against_single(b, imgs, masks, ctrs, key)
+    for i in range(0, len(imgs), 5):  # oracle directly
+        x = imgs[i].cpu().numpy()
+        ref = oracle.frag(x, masks[i], key, ctrs[i])
+        assert np.array_equal(b.privates[i].cpu().numpy()[: ref["cipher"].size], ref["cipher"])
+
+
+@pytest.mark.parametrize("tuning", [(1, 1), (4, 2), (16, 0), (1024, 3)])
+def test_tunings_give_identical_results(tuning):
+    imgs, masks, ctrs = _mixed(12, 5)
+    key = synth.aes_key(4)
+    b = Batch(imgs, masks, key, ctrs)
+    b.frag(tuning)
+    b.defrag(tuning)
+    torch.cuda.synchronize()
+    _check_against_single(b, imgs, masks, ctrs, key)
+
+
+def test_graph_replays_and_autotune(tmp_path):
+    imgs, masks, ctrs = _mixed(16, 6)
+    key = synth.aes_key(4)
+    b = Batch(imgs, masks, key, ctrs)
+    tuning, ms = b.autotune(cache=str(tmp_path / "tune.json"))
+    assert tuning[0] in (1, 2, 4, 8, 16) and 1 <= tuning[1] <= 3 and ms > 0
+    assert b.autotune(cache=str(tmp_path / "tune.json"))[0] == tuning  # cached
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            b.frag()
+            b.defrag()
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for r in b.restored:
+            r.zero_()
+        for p in b.publics:
+            p.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check_against_single(b, imgs, masks, ctrs, key)
+
+
+def test_batch_plan_rejects_bad_items():
+    x = torch.zeros((1, 16, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(sf.SefragError):
+        Batch([x, torch.zeros((1, 12, 16), dtype=torch.uint8, device="cuda")], [3, 3], None, [bytes(16)] * 2)
+
+
+def test_workload4_2000_images():
+    """2000 images (sides log-uniform in [256, 4096], 1 or 3 channels, k from
+    {1, 2, 5, 9}, per-image nonce): every round trip exact on the GPU; 256
+    sampled blocks of 16 images (across k and C) compared with the oracle."""
+    specs = synth.batch_specs()
+    key = synth.aes_key(4)
+    imgs, masks, ctrs = [], [], []
+    for i, (H, W, C, k) in enumerate(specs):
+        imgs.append(synth.image(H, W, C, 4, i, device="cuda"))
+        masks.append(sf.prefix_mask(k))
+        ctrs.append(synth.ctr0(4, i))
+    print("case: workload 4, %d images, %.2f G samples" % (len(imgs), sum(x.numel() for x in imgs) / 1e9), flush=True)
+    b = Batch(imgs, masks, key, ctrs)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.frag(status=status)
+    b.defrag(status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    for i, x in enumerate(imgs):
+        assert torch.equal(b.restored[i], x), "image %d round trip" % i
+    rng = np.random.default_rng(44)
+    chosen = []
+    for k in (1, 2, 5, 9):
+        for C in (1, 3):
+            idx = [i for i, s in enumerate(specs) if s[3] == k and s[2] == C]
+            chosen += list(rng.choice(idx, 2, replace=False))
+    for i in chosen:
+        H, W, C, k = specs[i]
+        x = imgs[i]
+        nb = C * H * W // 64
+        npriv, npub = k + 1, 63 - k
+        blocks = np.sort(rng.choice(nb, min(256, nb), replace=False))
+        xb = x.view(C, H // 8, 8, W // 8, 8).permute(0, 1, 3, 2, 4).reshape(nb, 64)[torch.from_numpy(blocks).cuda()]
+        xb = xb.cpu().numpy()
+        strip = xb.reshape(-1, 8, 8).transpose(1, 0, 2).reshape(8, -1)[None]
+        ref = oracle.frag(strip, masks[i])
+        ref_priv = oracle.tile_unpack(ref["private"], blocks.size, npriv)
+        ref_pub = oracle.tile_unpack(ref["public"], blocks.size, npub)
+        prv = b.privates[i].cpu().numpy()
+        for j in range(npriv):
+            byte = 2 * oracle.tile_offsets(nb, npriv, blocks, j)
+            ks = oracle.ctr_keystream(key, ctrs[i], byte // 16)
+            k0 = ks[np.arange(byte.size), byte % 16]
+            k1 = ks[np.arange(byte.size), byte % 16 + 1]
+            plain = (prv[byte] ^ k0).astype(np.uint16) | ((prv[byte + 1] ^ k1).astype(np.uint16) << 8)
+            assert np.array_equal(plain.view(np.int16), ref_priv[:, j])
+        pidx = oracle.tile_offsets(nb, npub, np.repeat(blocks, npub), np.tile(np.arange(npub), blocks.size))
+        got = b.publics[i][torch.from_numpy(pidx).cuda()].cpu().numpy().astype(np.float64).reshape(blocks.size, npub)
+        nrm = np.linalg.norm(xb.astype(np.float64), axis=1)
+        err = np.linalg.norm(got - ref_pub, axis=1)
+        assert np.all(err[nrm == 0] == 0)
+        assert (err[nrm > 0] / nrm[nrm > 0]).max() <= 1e-5

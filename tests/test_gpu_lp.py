@@ -18,7 +18,25 @@ sf = pytest.importorskip("paper_1512_02951_amd")
 pytestmark = pytest.mark.gpu
 
 TOL_LP = 2e-3
-DT = {"fp16": np.float16, "bf16": None}
+# bf16 keeps 8 significant bits: storing a coefficient alone can move it by
+# up to 2^-8 of its value.  When the dominant coefficients (DC first) are
+# private, the public part is small next to the block norm and 2e-3 holds;
+# when DC itself is public the stored values can only be held to the storage
+# bound (plus the transform's own error).
+TOL_BF16_DC_PUBLIC = 2.0 ** -8 + 2e-4
+
+
+def _round_like(v: np.ndarray, prec: str) -> np.ndarray:
+    """Oracle values rounded to the storage type (round to nearest even)."""
+    if prec == "fp16":
+        return v.astype(np.float16).astype(np.float64)
+    return torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _ulp(v: np.ndarray, prec: str) -> np.ndarray:
+    mant = 10 if prec == "fp16" else 7
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -14)))
+    return 2.0 ** (e - mant)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -55,8 +73,12 @@ def _check(x, mask, prec, key=None, ctr0=None, label=""):
         zero = nrm == 0
         assert np.all(err[zero] == 0), "all-zero block not exactly zero"
         rel = err[~zero] / nrm[~zero]
-        assert rel.size == 0 or rel.max() <= TOL_LP, "public rel err %g" % rel.max()
+        tol = TOL_LP if (prec == "fp16" or mask & 1) else TOL_BF16_DC_PUBLIC
+        assert rel.size == 0 or rel.max() <= tol, "public rel err %g" % rel.max()
         print("  public max normwise rel err %.3e" % (rel.max() if rel.size else 0.0), flush=True)
+        # the transform itself: stored values are the oracle's rounded values, within one unit in the last place
+        rounded = _round_like(pub_ref, prec)
+        assert np.all(np.abs(pub - rounded) <= _ulp(rounded, prec) * (1 + 1e-9)), "stored value off by > 1 ulp"
     r = fr.residual.cpu().numpy()
     print("  residual nonzero fraction %.3e, max |r| %d" % (np.count_nonzero(r) / r.size, np.abs(r.astype(int)).max()),
           flush=True)
