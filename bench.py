@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 H, W, C, K_PRIV = 4096, 4096, 3, 5
+COPY_BYTES = 256 << 20
 
 
 def algorithmic_bytes(H, W, C, npriv, pub_elt=4):
@@ -111,6 +112,103 @@ def measure(sf, torch, sets, mask, key, status, steps, warmup):
     return ms, frag_ms, defrag_ms
 
 
+def _bytes_plain(H, W, C, npriv, pub_elt=4, residual=False):
+    return algorithmic_bytes(H, W, C, npriv, pub_elt) + (H * W * C if residual else 0)
+
+
+def measure_forms(sf, torch, synth, dev, steps, warmup):
+    """Companion figures for the three forms, each on its own workload (these
+    are not the headline number): the precision form (16 images 8192^2 gray,
+    DC + 9 AC private) as FP32 vs fp16 vs bf16 round trips; the batching form
+    (2000 mixed images) with the tuner's schedule; the differentiation form
+    (64 x 1024^2 FP32): statistics pass, forward with P, adjoint backward and
+    the 200-step tuning loop.  Every figure is a HIP-graph replay average."""
+    from paper_1512_02951_amd import softmask as sm
+    from paper_1512_02951_amd.batch import Batch
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {}
+
+    # ---- precision form
+    n_img, S, k = 16, 8192, 9
+    mask, key = sf.prefix_mask(k), synth.aes_key(3)
+    xs = [synth.image(S, S, 1, 3, i, device=dev) for i in range(n_img)]
+    ctrs = [synth.ctr0(3, i) for i in range(n_img)]
+    prec_res = {}
+    for prec in ("fp32", "fp16", "bf16"):
+        frs = [sf.frag_image(x, mask, key, c, precision=prec) for x, c in zip(xs, ctrs)]
+        ys = [torch.empty_like(x) for x in xs]
+
+        def rt(frs=frs, ys=ys, prec=prec):
+            for x, c, fr, y in zip(xs, ctrs, frs, ys):
+                sf.frag_image(x, mask, key, c, precision=prec, out=fr, status=status)
+                sf.defrag_image(fr, key, c, out=y, status=status)
+        g = capture(torch, rt)
+        ms = time_graphs(torch, [g], steps, warmup)
+        assert int(status.item()) == 0 and all(torch.equal(x, y) for x, y in zip(xs, ys))
+        lp = prec != "fp32"
+        nbytes = 2 * n_img * _bytes_plain(S, S, 1, k + 1, 2 if lp else 4, residual=lp)
+        prec_res[prec] = {"ms_per_step": round(ms, 4), "MP/s": round(n_img * S * S / 1e6 / (ms * 1e-3), 1),
+                          "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+        del frs, ys, g
+    out["precision"] = {"workload": "16 x 8192^2 gray uint8, DC+9 AC private, round trip (exact)",
+                        "public_accuracy": "fp16/bf16 public within 2e-3 normwise of the FP64 oracle "
+                                           "(bf16 with public DC: storage bound 2^-8); FP32 within 1e-5",
+                        **prec_res}
+    del xs
+
+    # ---- batching form
+    specs = synth.batch_specs()
+    bkey = synth.aes_key(4)
+    imgs = [synth.image(h, w, c, 4, i, device=dev) for i, (h, w, c, kk) in enumerate(specs)]
+    b = Batch(imgs, [sf.prefix_mask(kk) for (_, _, _, kk) in specs], bkey, [synth.ctr0(4, i) for i in range(len(specs))])
+    tuning, tune_ms = b.autotune()
+
+    def brt():
+        b.frag(status=status)
+        b.defrag(status=status)
+    b.frag(status=status)
+    gb = capture(torch, brt)
+    ms = time_graphs(torch, [gb], max(steps // 4, 3), warmup)
+    assert int(status.item()) == 0 and all(torch.equal(x, y) for x, y in zip(imgs, b.restored))
+    samples = sum(x.numel() for x in imgs)
+    nbytes = 2 * sum(_bytes_plain(h, w, c, kk + 1) for (h, w, c, kk) in specs)
+    out["batching"] = {"workload": "2000 images, sides log-uniform in [256, 4096], C in {1, 3}, k in {1, 2, 5, 9}, "
+                                   "one persistent kernel per direction, HIP graph",
+                       "tiles_per_grab": tuning[0], "workgroups_per_cu": tuning[1],
+                       "ms_per_step": round(ms, 4), "MP/s": round(samples / 1e6 / (ms * 1e-3), 1),
+                       "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    del imgs, b, gb
+
+    # ---- differentiation form
+    B, Hs, Ws = 64, 1024, 1024
+    x = synth.softmask_images(B, Hs, Ws, device=dev)
+    l = torch.from_numpy(synth.logits_init().astype("float32")).to(dev)
+    G = torch.empty_like(x).normal_()
+    sm.forward(x, l)
+    sm.backward(x, G, l)
+    nsamp = B * Hs * Ws
+    res = {}
+    for name, fn, bps in (("statistics", lambda: sm.forward(x, l, public=False), 4),
+                          ("forward_with_P", lambda: sm.forward(x, l), 8),
+                          ("adjoint_backward", lambda: sm.backward(x, G, l), 8)):
+        g = capture(torch, fn)
+        ms = time_graphs(torch, [g], steps, warmup)
+        res[name] = {"ms": round(ms, 4), "GB/s": round(nsamp * bps / (ms * 1e-3) / 1e9, 1)}
+    _, stats = sm.forward(x, l, public=False)
+    lt = l.clone()
+    trace = torch.empty(200, dtype=torch.float64, device=dev)
+    mask_t = torch.zeros(1, dtype=torch.int64, device=dev)
+    L = sm.lib()
+    import ctypes
+    tune_args = (ctypes.c_void_p(stats.data_ptr()), B, Hs, Ws, sm.LAMBDA, sm.BUDGET, 200, 0.05,
+                 ctypes.c_void_p(lt.data_ptr()), ctypes.c_void_p(trace.data_ptr()), ctypes.c_void_p(mask_t.data_ptr()),
+                 6)
+    gt = capture(torch, lambda: sf.check(L.sf_softmask_tune(*tune_args, sf._stream(None))))
+    res["tune_200_adam_steps"] = {"ms": round(time_graphs(torch, [gt], 5, 1), 4)}
+    out["differentiation"] = {"workload": "64 x 1024^2 FP32 in [0, 1], soft mask over 64 frequencies", **res}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +217,9 @@ def main():
     ap.add_argument("--sets", type=int, default=4, help="disjoint buffer sets rotated across steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-forms", action="store_true", help="skip the companion figures of the three forms")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 256 MiB buffer 3 times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
@@ -131,6 +232,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        a = torch.full((COPY_BYTES,), 3, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)  # reads and writes COPY_BYTES each
+        torch.cuda.synchronize()
+        del a, b
     mask = sf.prefix_mask(K_PRIV)
     key = synth.aes_key(2)
     sets = make_sets(sf, synth, torch, dev, args.sets, mask, key)
@@ -170,6 +278,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": per_launch},
     }
+    if not args.no_forms:
+        del sets
+        torch.cuda.empty_cache()
+        out["forms"] = measure_forms(sf, torch, synth, dev, max(args.steps // 10, 5), 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -225,6 +225,69 @@ int sf_defrag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint
  * Runs the batch many times (outputs are rewritten with identical values). */
 int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *best_ms, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Differentiation form: a soft per-frequency selection mask
+ * m_n = sigmoid(l_n) over the 64 natural frequencies n = 8u + v, and the
+ * public image it leaves, P = IDCT(DCT(x) * (1 - m)) per 8x8 block (the
+ * hard-mask case is the zero-padded public image of Sec. 6.3.1 / Fig. 7b).
+ * Images: B planes of H x W float32 (H, W multiples of 8), contiguous.
+ * The tuning objective is the mean over images of the squared Pearson
+ * correlation of P and x (Sec. 6.6.2, population moments) plus
+ * lam * (sum_n m_n - budget)^2.  Statistics are FP64.
+ * ------------------------------------------------------------------- */
+
+/* Device workspace bytes for the soft-mask calls on B x H x W images. */
+size_t sf_softmask_workspace_bytes(uint32_t B, uint32_t H, uint32_t W);
+
+/* Forward: d_public (may be NULL) <- P; d_stats (B x 65 doubles) <- per image
+ * E_n = sum over blocks of DCT(x)_n^2 (n = 0..63), then sum x. */
+int sf_softmask_forward(const float *d_x, uint32_t B, uint32_t H, uint32_t W, const float *d_logits,
+                        float *d_public, double *d_stats, void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* Correlation statistics of an arbitrary P: d_stats (B x 5 doubles) <-
+ * sum x, sum P, sum xP, sum x^2, sum P^2 per image. */
+int sf_softmask_corr_stats(const float *d_x, const float *d_public, uint32_t B, uint32_t H, uint32_t W,
+                           double *d_stats, void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* Loss from statistics.  mode 0: d_stats from sf_softmask_forward (P implied
+ * by the mask, correlation terms by Parseval: sum xP = sum_n (1-m_n) E_n,
+ * sum P^2 = sum_n (1-m_n)^2 E_n, mean P = (1-m_0) mean x); mode 1: d_stats
+ * from sf_softmask_corr_stats.  Outputs (each may be NULL): *d_loss;
+ * d_grad_logits (64, mode 0 only): the whole dL/dl in closed form;
+ * d_grad_budget (64): the budget term's dL/dl; d_gcoef (B x 4 floats:
+ * a, b, mean x, mean P) with dL/dP = a (x - mean x) + b (P - mean P). */
+int sf_softmask_loss(const double *d_stats, int mode, const float *d_logits, uint32_t B, uint32_t H, uint32_t W,
+                     float lam, float budget, double *d_loss, float *d_grad_logits, float *d_grad_budget,
+                     float *d_gcoef, void *stream);
+
+/* d_grad_public <- s * (a (x - mean x) + b (P - mean P)) per image, from the
+ * d_gcoef written by sf_softmask_loss, with s = *d_scale (a device double,
+ * the upstream gradient of the loss; NULL means 1).  If d_grad_budget (64
+ * floats from sf_softmask_loss) is given, d_grad_logits (64) <- s times it. */
+int sf_softmask_corr_grad(const float *d_x, const float *d_public, uint32_t B, uint32_t H, uint32_t W,
+                          const float *d_gcoef, const double *d_scale, float *d_grad_public, const float *d_grad_budget,
+                          float *d_grad_logits, void *stream);
+
+/* The tuning loop on the statistics of sf_softmask_forward (the mode 0
+ * closed form needs no further pass over the images): `steps` Adam updates
+ * (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) of d_logits in place, the
+ * loss before each update into d_loss_trace (steps doubles, may be NULL),
+ * then the n_private largest logits (ties to the lower n) hardened into a
+ * private_mask bit set (bit n = natural frequency n) at *d_private_mask (may
+ * be NULL) for frag_image.  Minimising the correlation of the public image
+ * with the input under the budget picks the coefficients whose removal hides
+ * the most (Sec. 6.6.2 measures protection by this correlation). */
+int sf_softmask_tune(const double *d_stats, uint32_t B, uint32_t H, uint32_t W, float lam, float budget,
+                     uint32_t steps, float lr, float *d_logits, double *d_loss_trace, uint64_t *d_private_mask,
+                     uint32_t n_private, void *stream);
+
+/* Adjoint (backward) of the forward for an arbitrary upstream gradient
+ * G = dL/dP: d_grad_logits (64) <- sigmoid'(l_n) * (- sum over images and
+ * blocks of DCT(G)_n DCT(x)_n), the transposed transform applied to G. */
+int sf_softmask_backward(const float *d_x, const float *d_grad_public, uint32_t B, uint32_t H, uint32_t W,
+                         const float *d_logits, float *d_grad_logits, void *d_workspace, size_t workspace_bytes,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -362,3 +362,55 @@ def softmask_grad(x: np.ndarray, logits: np.ndarray, lam: float = LAMBDA, budget
     loss = float((rhos ** 2).mean() + lam * (m.sum() - budget) ** 2)
     grad = m * (1.0 - m) * (dm + 2.0 * lam * (m.sum() - budget))
     return grad, loss, rhos
+
+
+def softmask_stats(x: np.ndarray):
+    """Per image: E_n = sum over blocks of DCT(x)_n^2 (64 values, natural
+    order) and the sample sum; the statistics the closed-form loss needs."""
+    x = np.asarray(x, np.float64)
+    Bm = basis()
+    E = np.empty((x.shape[0], 64))
+    sx = np.empty(x.shape[0])
+    for i in range(x.shape[0]):
+        blk = _img_blocks(x[i])
+        E[i] = ((blk @ Bm.T) ** 2).sum(0)
+        sx[i] = blk.sum()
+    return E, sx
+
+
+def softmask_adam(x: np.ndarray, logits: np.ndarray, steps: int, lr: float, lam: float = LAMBDA,
+                  budget: float = BUDGET):
+    """Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the logits with the adjoint
+    gradient of softmask_grad.  Returns (logits, loss before each step)."""
+    l = np.array(logits, np.float64)
+    mom = np.zeros(64)
+    vel = np.zeros(64)
+    trace = []
+    for t in range(1, steps + 1):
+        g, loss, _ = softmask_grad(x, l, lam, budget)
+        trace.append(loss)
+        mom = 0.9 * mom + 0.1 * g
+        vel = 0.999 * vel + 0.001 * g * g
+        l = l - lr * (mom / (1 - 0.9 ** t)) / (np.sqrt(vel / (1 - 0.999 ** t)) + 1e-8)
+    return l, np.array(trace)
+
+
+def harden(logits: np.ndarray, n_private: int) -> int:
+    """Bit set of the n_private largest logits (ties to the lower index),
+    bit n = natural frequency n."""
+    order = sorted(range(64), key=lambda n: (-float(logits[n]), n))
+    return sum(1 << n for n in order[:n_private])
+
+
+def softmask_adjoint(x: np.ndarray, G: np.ndarray, logits: np.ndarray) -> np.ndarray:
+    """Gradient of the linear functional <G, P(logits)> with respect to the
+    logits: sigmoid'(l_n) * (- sum over images and blocks of DCT(G)_n DCT(x)_n),
+    the transposed transform applied to G."""
+    x = np.asarray(x, np.float64)
+    G = np.asarray(G, np.float64)
+    Bm = basis()
+    acc = np.zeros(64)
+    for i in range(x.shape[0]):
+        acc += ((_img_blocks(G[i]) @ Bm.T) * (_img_blocks(x[i]) @ Bm.T)).sum(0)
+    m = sigmoid(logits)
+    return m * (1.0 - m) * -acc

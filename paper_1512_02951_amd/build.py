@@ -9,6 +9,8 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -19,7 +21,6 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "--offload-arch=gfx950",
     "-fPIC",
-    "-shared",
     # every FMA in the kernels is explicit; no implicit contraction
     "-ffp-contract=off",
     # keep the compiler from forming packed FP32 instructions
@@ -40,25 +41,34 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, extra=(), out: str | None = None) -> str:
-    """Compile every HIP source into libsefrag.so (always recompiles).
-    ``extra`` adds compiler flags (e.g. -D tuning knobs); ``out`` writes the
-    library elsewhere."""
-    lib = out or LIB
-    tmp = lib + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           "-o", tmp, *sources()]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building libsefrag.so")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
     if verbose and proc.stderr:
         # hipcc's host pass warns about the GPU-only target feature; show the rest
         lines = [l for l in proc.stderr.splitlines() if "packed-fp32-ops" not in l]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
+
+
+def build(verbose: bool = False, extra=(), out: str | None = None, jobs: int | None = None) -> str:
+    """Compile every HIP source (in parallel) and link libsefrag.so; always
+    recompiles.  ``extra`` adds compiler flags (e.g. -D tuning knobs); ``out``
+    writes the library elsewhere."""
+    lib = out or LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    jobs = jobs or min(8, len(sources()), os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="sefrag_build_") as objdir:
+        objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in sources()]
+        cmds = [[hipcc(), *HIPCC_FLAGS, *extra, *inc, "-c", "-o", o, src] for src, o in zip(sources(), objs)]
+        with ThreadPoolExecutor(jobs) as pool:
+            list(pool.map(lambda c: _run(c, verbose), cmds))
+        _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, lib)
     return lib
 

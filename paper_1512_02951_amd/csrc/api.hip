@@ -269,6 +269,101 @@ int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *bes
   return rc;
 }
 
+// ---- differentiation form
+static int sm_ptrs(const void *a, const void *b) {
+  if (!a || !b) return fail(SF_EINVAL, "NULL buffer");
+  if (((uintptr_t)a | (uintptr_t)b) & 15u) return fail(SF_EINVAL, "buffers must be 16-byte aligned");
+  return SF_OK;
+}
+
+size_t sf_softmask_workspace_bytes(uint32_t B, uint32_t H, uint32_t W) {
+  DeviceState *ds;
+  if (device_state(&ds)) return 0;
+  return softmask_workspace_bytes(*ds, B, H, W);
+}
+
+int sf_softmask_forward(const float *d_x, uint32_t B, uint32_t H, uint32_t W, const float *d_logits,
+                        float *d_public, double *d_stats, void *d_workspace, size_t workspace_bytes, void *stream) {
+  int rc = sm_ptrs(d_x, d_stats);
+  if (rc) return rc;
+  if (!d_logits || !d_workspace || ((uintptr_t)d_public & 15u)) return fail(SF_EINVAL, "NULL or misaligned argument");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  rc = softmask_forward(*ds, d_x, B, H, W, d_logits, d_public, d_stats, d_workspace, workspace_bytes,
+                        (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_softmask_corr_stats(const float *d_x, const float *d_public, uint32_t B, uint32_t H, uint32_t W,
+                           double *d_stats, void *d_workspace, size_t workspace_bytes, void *stream) {
+  int rc = sm_ptrs(d_x, d_public);
+  if (rc) return rc;
+  if (!d_stats || !d_workspace) return fail(SF_EINVAL, "NULL argument");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  rc = softmask_corr_stats(*ds, d_x, d_public, B, H, W, d_stats, d_workspace, workspace_bytes, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_softmask_loss(const double *d_stats, int mode, const float *d_logits, uint32_t B, uint32_t H, uint32_t W,
+                     float lam, float budget, double *d_loss, float *d_grad_logits, float *d_grad_budget,
+                     float *d_gcoef, void *stream) {
+  if (!d_stats || !d_logits || !d_loss) return fail(SF_EINVAL, "NULL argument");
+  if (mode != 0 && mode != 1) return fail(SF_EINVAL, "mode must be 0 or 1");
+  if (mode == 1 && d_grad_logits) return fail(SF_EINVAL, "closed-form gradient needs mode 0 statistics");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  rc = softmask_loss(d_stats, mode, d_logits, B, H, W, lam, budget, d_loss, d_grad_logits, d_grad_budget, d_gcoef,
+                     (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_softmask_corr_grad(const float *d_x, const float *d_public, uint32_t B, uint32_t H, uint32_t W,
+                          const float *d_gcoef, const double *d_scale, float *d_grad_public, const float *d_grad_budget,
+                          float *d_grad_logits, void *stream) {
+  int rc = sm_ptrs(d_x, d_public);
+  if (rc) return rc;
+  if (!d_gcoef || !d_grad_public || ((uintptr_t)d_grad_public & 15u)) return fail(SF_EINVAL, "NULL or misaligned");
+  if (!d_grad_budget != !d_grad_logits) return fail(SF_EINVAL, "budget gradient input and output go together");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  rc = softmask_corr_grad(d_x, d_public, B, H, W, d_gcoef, d_scale, d_grad_public, d_grad_budget, d_grad_logits,
+                          (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_softmask_tune(const double *d_stats, uint32_t B, uint32_t H, uint32_t W, float lam, float budget,
+                     uint32_t steps, float lr, float *d_logits, double *d_loss_trace, uint64_t *d_private_mask,
+                     uint32_t n_private, void *stream) {
+  if (!d_stats || !d_logits) return fail(SF_EINVAL, "NULL argument");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  rc = softmask_tune(d_stats, B, H, W, lam, budget, steps, lr, d_logits, d_loss_trace, d_private_mask, n_private,
+                     (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_softmask_backward(const float *d_x, const float *d_grad_public, uint32_t B, uint32_t H, uint32_t W,
+                         const float *d_logits, float *d_grad_logits, void *d_workspace, size_t workspace_bytes,
+                         void *stream) {
+  int rc = sm_ptrs(d_x, d_grad_public);
+  if (rc) return rc;
+  if (!d_logits || !d_grad_logits || !d_workspace) return fail(SF_EINVAL, "NULL argument");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  rc = softmask_backward(*ds, d_x, d_grad_public, B, H, W, d_logits, d_grad_logits, d_workspace, workspace_bytes,
+                         (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
 int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *d_in, uint8_t *d_out,
                     size_t nbytes, void *stream) {
   if (!aes) return fail(SF_EINVAL, "aes is NULL");

@@ -201,6 +201,14 @@ __device__ __forceinline__ void aes_load_tables(AesLds &L, const uint32_t *__res
   for (int i = tid; i < 44; i += nthreads) L.rk[i] = K.rk[i];
 }
 
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // truth table of a ^ b ^ c
+}
+
+// One AES-128 encryption (FIPS-197 Sec. 5.1) of the state words s0..s3 with
+// the T-table formulation: each middle round is 16 table lookups whose byte
+// indices the compiler takes with sub-dword operand selection, and two
+// three-input XORs per column.
 __device__ __forceinline__ void aes_encrypt(uint32_t &s0, uint32_t &s1, uint32_t &s2, uint32_t &s3,
                                             const AesLds &L) {
   const uint32_t *rk = L.rk;
@@ -210,10 +218,14 @@ __device__ __forceinline__ void aes_encrypt(uint32_t &s0, uint32_t &s1, uint32_t
   s3 ^= rk[3];
 #pragma unroll
   for (int r = 1; r < 10; ++r) {
-    const uint32_t t0 = L.t[0][s0 & 0xff] ^ L.t[1][(s1 >> 8) & 0xff] ^ L.t[2][(s2 >> 16) & 0xff] ^ L.t[3][s3 >> 24] ^ rk[4 * r];
-    const uint32_t t1 = L.t[0][s1 & 0xff] ^ L.t[1][(s2 >> 8) & 0xff] ^ L.t[2][(s3 >> 16) & 0xff] ^ L.t[3][s0 >> 24] ^ rk[4 * r + 1];
-    const uint32_t t2 = L.t[0][s2 & 0xff] ^ L.t[1][(s3 >> 8) & 0xff] ^ L.t[2][(s0 >> 16) & 0xff] ^ L.t[3][s1 >> 24] ^ rk[4 * r + 2];
-    const uint32_t t3 = L.t[0][s3 & 0xff] ^ L.t[1][(s0 >> 8) & 0xff] ^ L.t[2][(s1 >> 16) & 0xff] ^ L.t[3][s2 >> 24] ^ rk[4 * r + 3];
+    const uint32_t t0 = xor3(xor3(L.t[0][s0 & 0xff], L.t[1][(s1 >> 8) & 0xff], L.t[2][(s2 >> 16) & 0xff]),
+                             L.t[3][s3 >> 24], rk[4 * r]);
+    const uint32_t t1 = xor3(xor3(L.t[0][s1 & 0xff], L.t[1][(s2 >> 8) & 0xff], L.t[2][(s3 >> 16) & 0xff]),
+                             L.t[3][s0 >> 24], rk[4 * r + 1]);
+    const uint32_t t2 = xor3(xor3(L.t[0][s2 & 0xff], L.t[1][(s3 >> 8) & 0xff], L.t[2][(s0 >> 16) & 0xff]),
+                             L.t[3][s1 >> 24], rk[4 * r + 2]);
+    const uint32_t t3 = xor3(xor3(L.t[0][s3 & 0xff], L.t[1][(s0 >> 8) & 0xff], L.t[2][(s1 >> 16) & 0xff]),
+                             L.t[3][s2 >> 24], rk[4 * r + 3]);
     s0 = t0;
     s1 = t1;
     s2 = t2;

@@ -100,6 +100,21 @@ int batch_run(const DeviceState &ds, const void *d_ws, int which, const sf_batch
               hipStream_t stream);
 int batch_autotune(const DeviceState &ds, const void *d_ws, sf_batch_tuning *best, float *best_ms,
                    hipStream_t stream);
+// Differentiation form (softmask.hip).
+size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, uint32_t W);
+int softmask_forward(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W, const float *logits,
+                     float *p_out, double *stats, void *ws, size_t ws_bytes, hipStream_t stream);
+int softmask_corr_stats(const DeviceState &ds, const float *x, const float *p, uint32_t B, uint32_t H, uint32_t W,
+                        double *stats, void *ws, size_t ws_bytes, hipStream_t stream);
+int softmask_backward(const DeviceState &ds, const float *x, const float *gpub, uint32_t B, uint32_t H, uint32_t W,
+                      const float *logits, float *grad_logits, void *ws, size_t ws_bytes, hipStream_t stream);
+int softmask_loss(const double *stats, int mode, const float *logits, uint32_t B, uint32_t H, uint32_t W, float lam,
+                  float budget, double *loss, float *grad_logits, float *grad_budget, float *gcoef,
+                  hipStream_t stream);
+int softmask_corr_grad(const float *x, const float *p, uint32_t B, uint32_t H, uint32_t W, const float *gcoef,
+                       const double *scale, float *g, const float *grad_budget, float *grad_out, hipStream_t stream);
+int softmask_tune(const double *stats, uint32_t B, uint32_t H, uint32_t W, float lam, float budget, uint32_t steps,
+                  float lr, float *logits, double *trace, uint64_t *mask, uint32_t n_private, hipStream_t stream);
 int launch_ctr(const DeviceState &ds, const AesArgs &aes, uint64_t first_block, const uint8_t *in, uint8_t *out,
                size_t nbytes, hipStream_t stream);
 

@@ -89,3 +89,49 @@ def test_adjoint_identity():
     b = rng.standard_normal((5, 64))
     Bm = oracle.basis()
     assert abs((oracle.idct_blocks(a) * b).sum() - (a * (b @ Bm.T)).sum()) < 1e-12
+
+
+def test_adjoint_of_public_image_matches_finite_differences():
+    # softmask_adjoint is d<G, P(l)>/dl; P is smooth in l, so central
+    # differences of the functional pin it
+    x = _images(B=2, H=16, W=32)
+    rng = np.random.default_rng(2)
+    G = rng.standard_normal(x.shape)
+    logits = synth.logits_init()
+    g = oracle.softmask_adjoint(x, G, logits)
+    h = 1e-4
+    fd = np.zeros(64)
+    for n in range(64):
+        e = np.zeros(64)
+        e[n] = h
+        fd[n] = ((G * oracle.softmask_public(x, logits + e)).sum() - (G * oracle.softmask_public(x, logits - e)).sum()) / (2 * h)
+    assert np.linalg.norm(fd - g) <= 1e-7 * np.linalg.norm(g)
+
+
+def test_statistics_are_block_sums():
+    x = _images(B=2, H=16, W=24)
+    E, sx = oracle.softmask_stats(x)
+    assert np.allclose(sx, x.reshape(2, -1).sum(1), rtol=1e-13)
+    # Parseval: the energies add up to the sum of squares
+    assert np.allclose(E.sum(1), (x ** 2).reshape(2, -1).sum(1), rtol=1e-12)
+    # DC energy: each block contributes (block sum / 8)^2
+    blk = x.reshape(2, 2, 8, 3, 8).sum(axis=(2, 4))
+    assert np.allclose(E[:, 0], (blk ** 2).sum(axis=(1, 2)) / 64.0, rtol=1e-12)
+
+
+def test_adam_descends_and_hardens_the_top_logits():
+    x = _images(B=2, H=16, W=24)
+    l0 = synth.logits_init()
+    l1, trace = oracle.softmask_adam(x, l0, steps=30, lr=0.05)
+    assert trace.shape == (30,)
+    assert trace[-1] < trace[0]
+    # the first step moves every logit by lr against the sign of its gradient
+    g, _, _ = oracle.softmask_grad(x, l0)
+    l_one, _ = oracle.softmask_adam(x, l0, steps=1, lr=0.05)
+    assert np.allclose(l_one - l0, -0.05 * np.sign(g), atol=1e-6)
+    mask = oracle.harden(l1, 6)
+    assert bin(mask).count("1") == 6
+    top = np.argsort(-l1, kind="stable")[:6]
+    assert mask == sum(1 << int(n) for n in top)
+    # ties go to the lower frequency
+    assert oracle.harden(np.zeros(64), 3) == 0b111
