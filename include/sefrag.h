@@ -273,8 +273,9 @@ int sf_softmask_corr_grad(const float *d_x, const float *d_public, uint32_t B, u
  * (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) of d_logits in place, the
  * loss before each update into d_loss_trace (steps doubles, may be NULL),
  * then the n_private largest logits (ties to the lower n) hardened into a
- * private_mask bit set (bit n = natural frequency n) at *d_private_mask (may
- * be NULL) for frag_image.  Minimising the correlation of the public image
+ * private_mask for frag_image at *d_private_mask (may be NULL): logit n
+ * belongs to natural frequency n, and bit z is set for the zigzag position z
+ * of each chosen frequency.  Minimising the correlation of the public image
  * with the input under the budget picks the coefficients whose removal hides
  * the most (Sec. 6.6.2 measures protection by this correlation). */
 int sf_softmask_tune(const double *d_stats, uint32_t B, uint32_t H, uint32_t W, float lam, float budget,

@@ -396,10 +396,13 @@ def softmask_adam(x: np.ndarray, logits: np.ndarray, steps: int, lr: float, lam:
 
 
 def harden(logits: np.ndarray, n_private: int) -> int:
-    """Bit set of the n_private largest logits (ties to the lower index),
-    bit n = natural frequency n."""
+    """private_mask of the n_private largest logits (ties to the lower natural
+    index): logit n belongs to natural frequency n, and the mask has bit z set
+    for the zigzag position z of each chosen frequency."""
     order = sorted(range(64), key=lambda n: (-float(logits[n]), n))
-    return sum(1 << n for n in order[:n_private])
+    pos = np.empty(64, np.int64)
+    pos[zigzag()] = np.arange(64)
+    return sum(1 << int(pos[n]) for n in order[:n_private])
 
 
 def softmask_adjoint(x: np.ndarray, G: np.ndarray, logits: np.ndarray) -> np.ndarray:

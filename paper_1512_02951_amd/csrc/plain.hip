@@ -44,15 +44,24 @@ struct DefragKernelArgs {
 #endif
 
 // Each wave walks tiles t, t + stride, ...
-template <class MP>
+// kQ2Mfma: the private AC integers come from int8 matrix products (at most
+// 16 private AC coefficients); each wave then owns kQ2StageBytes of LDS
+// after its private-byte staging area.
+template <class MP, bool kQ2Mfma>
 __global__ __launch_bounds__(kThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kernel(FragKernelArgs a) {
   __shared__ AesLds s_aes;
+  __shared__ Q2Operands s_q2[kQ2Mfma ? 64 : 1];  // B operand per lane (same for every wave)
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
+  if constexpr (kQ2Mfma)
+    if (threadIdx.x < 64) s_q2[lane] = q2_operands(a.o.q2, private_ac<MP>(a.g.mask, lane & 15), lane);
   __syncthreads();
-  uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
+  constexpr uint32_t kStage = kQ2Mfma ? kQ2StageBytes : 0u;
+  uint8_t *lp = s_dyn + wave * (a.lds_priv_bytes + kStage);
+  uint8_t *q2stage = lp + a.lds_priv_bytes;
+  const Q2Operands *Q = &s_q2[kQ2Mfma ? lane : 0];
   const uint32_t stride = gridDim.x * kWaves;
   uint32_t t = blockIdx.x * kWaves + wave;
   if (t >= a.g.ntiles) return;
@@ -69,7 +78,8 @@ __global__ __launch_bounds__(kThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kern
       Ln = tile_lane(a.g, tn, lane);
       load_block(a.g, Ln, xn);
     }
-    frag_tile<MP>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K);
+    frag_tile<MP, kQ2Mfma>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K,
+                           q2stage, Q);
     if (!more) break;
     t = tn;
     L = Ln;
@@ -77,11 +87,31 @@ __global__ __launch_bounds__(kThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kern
     for (int w = 0; w < 16; ++w) xs[w] = xn[w];
   }
 #else
-  for (; t < a.g.ntiles; t += stride) {
-    const TileLane L = tile_lane(a.g, t, lane);
+  if constexpr (kQ2Mfma) {
+    // the next tile's pixels are loaded from inside frag_tile, once the
+    // current ones have been consumed
+    TileLane L = tile_lane(a.g, t, lane);
     uint32_t xs[16];
     load_block(a.g, L, xs);
-    frag_tile<MP>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K);
+    for (;;) {
+      const uint32_t tn = t + stride;
+      const bool more = tn < a.g.ntiles;
+      const TileLane Ln = more ? tile_lane(a.g, tn, lane) : L;
+      frag_tile<MP, true>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K,
+                          q2stage, Q, [&]() {
+                            if (more) load_block(a.g, Ln, xs);
+                          });
+      if (!more) break;
+      t = tn;
+      L = Ln;
+    }
+  } else {
+    for (; t < a.g.ntiles; t += stride) {
+      const TileLane L = tile_lane(a.g, t, lane);
+      uint32_t xs[16];
+      load_block(a.g, L, xs);
+      frag_tile<MP, false>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K);
+    }
   }
 #endif
 }
@@ -112,10 +142,11 @@ int grid_for(const DeviceState &ds, const void *kernel, size_t lds, uint32_t nti
   return (int)(need < cap ? need : cap);
 }
 
-template <class MP>
-int launch_frag_mp(const DeviceState &ds, const FragKernelArgs &a, size_t lds, hipStream_t stream) {
-  const int grid = grid_for(ds, (const void *)&frag_fp32_kernel<MP>, lds, a.g.ntiles);
-  hipLaunchKernelGGL(frag_fp32_kernel<MP>, dim3(grid), dim3(kThreads), lds, stream, a);
+template <class MP, bool kQ2Mfma>
+int launch_frag_mp(const DeviceState &ds, const FragKernelArgs &a, hipStream_t stream) {
+  const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + (kQ2Mfma ? kQ2StageBytes : 0u));
+  const int grid = grid_for(ds, (const void *)&frag_fp32_kernel<MP, kQ2Mfma>, lds, a.g.ntiles);
+  hipLaunchKernelGGL((frag_fp32_kernel<MP, kQ2Mfma>), dim3(grid), dim3(kThreads), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "frag kernel launch");
 }
@@ -157,14 +188,16 @@ int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, f
   a.aes = aes;
   a.K = host_tables().dct;
   a.lds_priv_bytes = lds_priv_bytes(g);
-  const size_t lds = (size_t)kWaves * a.lds_priv_bytes;
-  // compile-time selections for DC + k AC, k in {1, 2, 5, 9}; any other mask at run time
+  // compile-time selections for DC + k AC, k in {1, 2, 5, 9}; any other mask
+  // at run time, on the matrix cores while at most 16 AC coefficients are private
   switch (g.mask) {
-    case (1ull << 2) - 1: return launch_frag_mp<MaskPrefix<2>>(ds, a, lds, stream);
-    case (1ull << 3) - 1: return launch_frag_mp<MaskPrefix<3>>(ds, a, lds, stream);
-    case (1ull << 6) - 1: return launch_frag_mp<MaskPrefix<6>>(ds, a, lds, stream);
-    case (1ull << 10) - 1: return launch_frag_mp<MaskPrefix<10>>(ds, a, lds, stream);
-    default: return launch_frag_mp<MaskRuntime>(ds, a, lds, stream);
+    case (1ull << 2) - 1: return launch_frag_mp<MaskPrefix<2>, true>(ds, a, stream);
+    case (1ull << 3) - 1: return launch_frag_mp<MaskPrefix<3>, true>(ds, a, stream);
+    case (1ull << 6) - 1: return launch_frag_mp<MaskPrefix<6>, true>(ds, a, stream);
+    case (1ull << 10) - 1: return launch_frag_mp<MaskPrefix<10>, true>(ds, a, stream);
+    default:
+      if (__builtin_popcountll(g.mask & ~1ull) <= kQ2MfmaMaxAc) return launch_frag_mp<MaskRuntime, true>(ds, a, stream);
+      return launch_frag_mp<MaskRuntime, false>(ds, a, stream);
   }
 }
 

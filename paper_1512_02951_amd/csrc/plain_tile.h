@@ -94,6 +94,14 @@ struct MaskRuntime {
   static constexpr int kNPriv = -1;
 };
 
+// Raw buffer resource over [base, base + bytes): per-tile fragment regions
+// are addressed as base (SGPRs) + lane offset (one VGPR) + coefficient offset
+// (an SGPR), so no 64-bit per-lane address arithmetic is spent per access.
+// Word 3 selects 32-bit untyped data.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 __device__ __forceinline__ uint64_t opaque_u64(uint64_t v) {
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
   asm volatile("" : "+s"(lo), "+s"(hi));
@@ -148,6 +156,92 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 __device__ __forceinline__ uint32_t byte_of(const uint32_t (&w)[16], int p) { return (w[p / 4] >> (8 * (p % 4))) & 0xffu; }
+
+// ---------------------------------------------------------------------------
+// Private integers of up to 16 AC coefficients of a tile as int8 matrix
+// products on the matrix cores (v_mfma_i32_16x16x64_i8): M = 16 blocks,
+// K = the block's 64 samples minus 128 (signed bytes), N = the private AC
+// coefficients.  One product per signed-byte limb of Bq, combined in the
+// accumulator as ((D_h 2^8) + D_m) 2^8 + D_l, then + 128 sum_p Bq: the same
+// integer acc as q2_acc (all arithmetic modulo 2^32, exact result in range).
+// Lane l holds A row l % 16 and B column l % 16 over samples 16 (l / 16) ..
+// 16 (l / 16) + 15; D row 4 (l / 16) + r (r = 0..3), column l % 16.  Pixels
+// reach the A layout through LDS (80-byte rows: conflict-free 16-byte reads);
+// accumulators return to the lane owning the block through LDS rows of 272
+// bytes per coefficient.
+typedef int q2v4 __attribute__((ext_vector_type(4)));
+typedef unsigned int q2u4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kQ2PixStride = 80;
+constexpr uint32_t kQ2AccStride = 272;
+constexpr uint32_t kQ2StageBytes = 64 * kQ2PixStride;  // also holds 16 rows of 272
+constexpr int kQ2MfmaMaxAc = 16;
+static_assert(kQ2StageBytes >= kQ2MfmaMaxAc * kQ2AccStride, "stage too small");
+
+struct Q2Operands {
+  q2v4 b[3];     // limbs l, m, h of column lane % 16, samples 16 (lane / 16) + 0..15
+  uint32_t bias;  // 128 sum_p Bq of that column
+};
+
+// Natural index of the a-th private AC coefficient (zigzag order), -1 if none.
+template <class MP>
+__device__ __forceinline__ int private_ac(uint64_t mask, int a) {
+  int n = -1, seen = 0;
+  static_for<1, 64>([&](auto zc) {
+    constexpr int z = decltype(zc)::value;
+    bool priv;
+    if constexpr (MP::kStatic) priv = z < MP::kNPriv;
+    else priv = (mask >> z) & 1u;
+    if (priv) {
+      if (seen == a) n = kZigZag.nat[z];
+      ++seen;
+    }
+  });
+  return n;
+}
+
+__device__ __forceinline__ Q2Operands q2_operands(const uint32_t *q2, int n, int lane) {
+  Q2Operands o;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int L = 0; L < 3; ++L)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o.b[L][j] = n >= 0 ? (int)q2[n * kQ2RowWords + 16 * L + 4 * g + j] : 0;
+  o.bias = n >= 0 ? q2[n * kQ2RowWords + 48] : 0u;
+  return o;
+}
+
+// xs: the lane's block as signed bytes (samples - 128); Qs: the lane's B
+// operand (kept in LDS by the kernel).  Leaves acc of AC
+// index a for block `lane` at stage + a * kQ2AccStride + 4 lane; the caller
+// issues wave_lds_sync() before reading it.
+__device__ __forceinline__ void q2_mfma(const uint32_t (&xs)[16], int lane, uint8_t *stage, const Q2Operands &Qs) {
+  uint4 *own = reinterpret_cast<uint4 *>(stage + lane * kQ2PixStride);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) own[j] = make_uint4(xs[4 * j], xs[4 * j + 1], xs[4 * j + 2], xs[4 * j + 3]);
+  wave_lds_sync();
+  q2v4 A[4];
+  const uint8_t *src = stage + (lane & 15) * kQ2PixStride + 16 * (lane >> 4);
+#pragma unroll
+  for (int bg = 0; bg < 4; ++bg) A[bg] = *reinterpret_cast<const q2v4 *>(src + 16 * bg * kQ2PixStride);
+  wave_lds_sync();
+  uint8_t *dst = stage + (lane & 15) * kQ2AccStride + 16 * (lane >> 4);
+  const Q2Operands Q = Qs;  // from LDS: not held in registers between tiles
+#pragma unroll
+  for (int bg = 0; bg < 4; ++bg) {
+    q2v4 c = {0, 0, 0, 0};
+    c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[bg], Q.b[2], c, 0, 0, 0);
+    c = (q2v4)((q2u4)c << 8u);
+    c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[bg], Q.b[1], c, 0, 0, 0);
+    c = (q2v4)((q2u4)c << 8u);
+    c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[bg], Q.b[0], c, 0, 0, 0);
+    c = (q2v4)((q2u4)c + Q.bias);
+    *reinterpret_cast<q2v4 *>(dst + 64 * bg) = c;
+  }
+}
+
+__device__ __forceinline__ int32_t q2_mfma_acc(const uint8_t *stage, uint32_t a, int lane) {
+  return reinterpret_cast<const int32_t *>(stage + a * kQ2AccStride)[lane];
+}
 
 // AES-CTR over the tile's private byte range [0, tbytes) held in LDS at lp;
 // writes the result to gp.  ctr_first = index of the tile's first AES block
@@ -234,10 +328,20 @@ __device__ __forceinline__ void load_block(const TileGeom &g, const TileLane &L,
   }
 }
 
-template <class MP>
+struct NoPrefetch {
+  __device__ void operator()() const {}
+};
+
+// kQ2Mfma: private AC integers from q2_mfma (at most 16 private AC
+// coefficients; q2stage and Q as set up by the kernel), else from q2_acc.
+// prefetch() (which may overwrite xs with the next tile's pixels) is called
+// once xs is dead, before the encryption pass, so those loads are in flight
+// during the rest of the tile.
+template <class MP, bool kQ2Mfma = false, class PF = NoPrefetch>
 __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, uint32_t t, const TileLane &L,
                                           uint32_t (&xs)[16], int lane, uint8_t *lp, const AesLds &s_aes, uint32_t enc,
-                                          uint64_t ctr_hi, uint64_t ctr_lo, const DctK &K) {
+                                          uint64_t ctr_hi, uint64_t ctr_lo, const DctK &K, uint8_t *q2stage = nullptr,
+                                          const Q2Operands *Q = nullptr, PF &&prefetch = PF{}) {
   const uint64_t b0 = L.b0;
   const uint32_t nt = L.nt;
   const bool valid = L.valid != 0u;
@@ -254,10 +358,14 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
 #pragma unroll
   for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // now pixels - 128, signed bytes
 
+  if constexpr (kQ2Mfma) q2_mfma(xs, lane, q2stage, *Q);
   fdct8x8(c, K);
+  if constexpr (kQ2Mfma) wave_lds_sync();
+  const uint32_t dc_priv = MP::kStatic ? 1u : (uint32_t)(mask & 1u);
 
   // ---- zigzag split
-  float *pub_tile = o.pub + b0 * g.npub;
+  const __amdgpu_buffer_rsrc_t pub_rs = buffer_rsrc(o.pub + b0 * g.npub, g.npub * nt * 4u);
+  const int pub_voff = lane * 4;
   const cu32_ptr q2 = as_const(o.q2) + opaque_zero();
   // cert = sum over private n of (|q_n - acc_n / 2^20| + E_n) * M_n bounds how far
   // the private rounding moves any reconstructed sample (table words kQ2Cert*).
@@ -273,7 +381,9 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
           cert += (float)(d < 0 ? -d : d) * (0.125f * 0.125f);  // M_0 = 1/8, E_0 = 0
         } else {
           const cu32_ptr row = q2 + n * kQ2RowWords;
-          const int32_t acc = q2_acc(xs, row);
+          int32_t acc;
+          if constexpr (kQ2Mfma) acc = q2_mfma_acc(q2stage, pr - dc_priv, lane);
+          else acc = q2_acc(xs, row);
           q = q2_round(acc);
           const int32_t d = (int32_t)((uint32_t)q << 20) - acc;  // |d| <= 2^19
           const float e = __builtin_fmaf((float)(d < 0 ? -d : d), 0x1p-20f, __uint_as_float(row[kQ2CertE]));
@@ -284,7 +394,7 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
       },
       [&](auto nc, uint32_t pu) {
         constexpr int n = decltype(nc)::value;
-        if (valid) pub_tile[pu * nt + lane] = c[n];
+        if (valid) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c[n]), pub_rs, pub_voff, (int)(pu * nt * 4u), 0);
       });
 
   // ---- reconstruction check on exactly the stored values, for waves holding
@@ -295,12 +405,18 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
       idct8x8(c, K);
 #pragma unroll
       for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // back to pixel bytes
-      uint64_t bad = 0;
+      // miss bits placed with v_lshl_or_b32 (shift amount inline), which the
+      // optimiser would otherwise turn into selects of 64 bit constants held
+      // in registers across the whole tile loop
+      uint32_t bad_lo = 0, bad_hi = 0;
       static_for<0, 64>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
-        bad |= (r != (float)byte_of(xs, p)) ? (1ull << p) : 0ull;
+        const uint32_t miss = r != (float)byte_of(xs, p) ? 1u : 0u;
+        uint32_t &acc = p < 32 ? bad_lo : bad_hi;
+        asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(acc) : "v"(miss), "i"(p & 31));
       });
+      uint64_t bad = (uint64_t)bad_lo | ((uint64_t)bad_hi << 32);
       if (!valid) bad = 0;
       uint32_t slot = wave_exclusive_scan((uint32_t)__builtin_popcountll(bad), lane, total);
       while (bad) {
@@ -318,6 +434,9 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
     if (lane == 0) o.exc.count[t] = (uint16_t)(total < 65535u ? total : 65535u);
   }
 
+  // the pixel words are dead from here on
+  prefetch();
+
   // ---- private bytes of the tile: AES-CTR, 16 bytes per lane, coalesced
   wave_lds_sync();
   tile_ctr_store(lp, o.priv + b0 * g.npriv * 2u, 2u * g.npriv * nt, lane, s_aes, enc, ctr_hi, ctr_lo,
@@ -334,22 +453,29 @@ __device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &i
   const bool valid = L.valid != 0u;
   const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
 
+  // public values first: their loads stay in flight while the private bytes
+  // are decrypted
+  float c[64];
+  const __amdgpu_buffer_rsrc_t pub_rs = buffer_rsrc(in.pub + b0 * g.npub, g.npub * nt * 4u);
+  // lanes past the tile's last block read lane 0's values (in range); their
+  // results are never stored
+  const int pub_voff = valid ? lane * 4 : 0;
+  for_each_coef<MP>(
+      mask, [&](auto, uint32_t) {},
+      [&](auto nc, uint32_t pu) {
+        constexpr int n = decltype(nc)::value;
+        c[n] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(pub_rs, pub_voff, (int)(pu * nt * 4u), 0));
+      });
   tile_ctr_load(lp, in.priv + b0 * g.npriv * 2u, 2u * g.npriv * nt, lane, s_aes, enc, ctr_hi, ctr_lo,
                 b0 * g.npriv / 8u);
   wave_lds_sync();
-
-  float c[64];
-  const float *pub_tile = in.pub + b0 * g.npub;
   for_each_coef<MP>(
       mask,
       [&](auto nc, uint32_t pr) {
         constexpr int n = decltype(nc)::value;
         c[n] = valid ? (float)*reinterpret_cast<const int16_t *>(lp + 2u * (pr * nt + lane)) : 0.0f;
       },
-      [&](auto nc, uint32_t pu) {
-        constexpr int n = decltype(nc)::value;
-        c[n] = valid ? pub_tile[pu * nt + lane] : 0.0f;
-      });
+      [&](auto, uint32_t) {});
   wave_lds_sync();
 
   idct8x8(c, K);
@@ -361,12 +487,12 @@ __device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &i
       uint32_t w[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
+        // v_cvt_pk_u8_f32 rounds half to even and saturates to [0, 255]
+        // (checked on gfx950 over the half-integers, the range edges and
+        // 4096 values in [-20, 527)): one instruction per sample
         uint32_t acc = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float v = __builtin_amdgcn_fmed3f(__builtin_rintf(c[8 * r + 4 * h + i]), 0.0f, 255.0f);
-          acc |= (uint32_t)v << (8 * i);
-        }
+        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_cvt_pk_u8_f32(c[8 * r + 4 * h + i], i, acc);
         w[h] = acc;
       }
       *reinterpret_cast<uint2 *>(p + (size_t)r * g.W) = make_uint2(w[0], w[1]);

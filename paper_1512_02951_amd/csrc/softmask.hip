@@ -386,7 +386,7 @@ __global__ __launch_bounds__(64) void sm_loss_kernel(LossArgs a, const float *lo
 // The whole tuning loop on fixed statistics: Adam on the 64 logits
 // (beta1 0.9, beta2 0.999, eps 1e-8), loss before each step into trace, then
 // the n_private largest logits (ties to the lower frequency) hardened into a
-// selection bitmask over natural indices n = 8u + v.
+// private_mask: bit z set for the zigzag position z of each chosen frequency.
 __global__ __launch_bounds__(64) void sm_tune_kernel(LossArgs a, float *logits, uint32_t steps, double lr,
                                                      double *trace, uint64_t *mask_out, uint32_t n_private) {
   __shared__ LossShared S;
@@ -410,7 +410,11 @@ __global__ __launch_bounds__(64) void sm_tune_kernel(LossArgs a, float *logits, 
   __syncthreads();
   uint32_t rank = 0;
   for (int k = 0; k < 64; ++k) rank += (s_l[k] > s_l[n]) || (s_l[k] == s_l[n] && k < n);
-  const uint64_t bits = __ballot(rank < n_private);
+  // lane z of the ballot asks whether the frequency at zigzag position z is chosen
+  __shared__ uint32_t s_sel[64];
+  s_sel[kZigZagInv.pos[n]] = rank < n_private ? 1u : 0u;
+  __syncthreads();
+  const uint64_t bits = __ballot(s_sel[n] != 0u);
   if (mask_out && n == 0) mask_out[0] = bits;
 }
 

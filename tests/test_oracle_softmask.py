@@ -131,7 +131,12 @@ def test_adam_descends_and_hardens_the_top_logits():
     assert np.allclose(l_one - l0, -0.05 * np.sign(g), atol=1e-6)
     mask = oracle.harden(l1, 6)
     assert bin(mask).count("1") == 6
-    top = np.argsort(-l1, kind="stable")[:6]
-    assert mask == sum(1 << int(n) for n in top)
-    # ties go to the lower frequency
-    assert oracle.harden(np.zeros(64), 3) == 0b111
+    zz = oracle.zigzag()
+    top = set(int(n) for n in np.argsort(-l1, kind="stable")[:6])
+    assert {int(zz[z]) for z in range(64) if (mask >> z) & 1} == top
+    # logits falling along the zigzag walk harden into DC + the first 5 AC
+    ramp = np.empty(64)
+    ramp[zz] = -np.arange(64.0)
+    assert oracle.harden(ramp, 6) == 0b111111
+    # ties go to the lower natural index: n = 0, 1, 2 sit at zigzag 0, 1, 5
+    assert oracle.harden(np.zeros(64), 3) == 0b100011
