@@ -142,22 +142,29 @@ class _Eager:
         self.fn()
 
 
-def measure(sf, torch, sets, mask, key, status, steps, warmup, eager=False):
-    """Round-trip time per step (graph per buffer set: frag + defrag), and the
-    per-launch durations of frag and defrag alone (graphs of one call)."""
+def measure(sf, torch, sets, mask, key, status, steps, warmup, graph=False):
+    """Round-trip time per step (frag_image + defrag_image on one stream,
+    buffer sets in rotation), then the split of a step between the two
+    kernels: events recorded on the same stream before frag, between the two
+    launches and after defrag, in a second pass of the same loop.  With graph,
+    each step is one HIP-graph replay instead of two direct launches."""
     def rt(x, fr, y, c0):
         sf.frag_image(x, mask, key, c0, out=fr, status=status)
         sf.defrag_image(fr, key, c0, out=y, status=status)
-    if eager:
-        capture = lambda torch, fn: _Eager(fn)  # noqa: E731
-    else:
-        capture = _capture
-    g_rt = [capture(torch, lambda a=a: rt(*a)) for a in sets]
-    g_f = [capture(torch, lambda a=a: sf.frag_image(a[0], mask, key, a[3], out=a[1], status=status)) for a in sets]
-    g_d = [capture(torch, lambda a=a: sf.defrag_image(a[1], key, a[3], out=a[2], status=status)) for a in sets]
-    ms = time_graphs(torch, g_rt, steps, warmup)
-    frag_ms = time_graphs(torch, g_f, steps, warmup)
-    defrag_ms = time_graphs(torch, g_d, steps, warmup)
+    fns = [lambda a=a: rt(*a) for a in sets]
+    runners = [_capture(torch, f) for f in fns] if graph else [_Eager(f) for f in fns]
+    ms = time_graphs(torch, runners, steps, warmup)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for i in range(steps):
+        x, fr, y, c0 = sets[i % len(sets)]
+        ev[i][0].record()
+        sf.frag_image(x, mask, key, c0, out=fr, status=status)
+        ev[i][1].record()
+        sf.defrag_image(fr, key, c0, out=y, status=status)
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    frag_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    defrag_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
     return ms, frag_ms, defrag_ms
 
 
@@ -171,7 +178,8 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
     DC + 9 AC private) as FP32 vs fp16 vs bf16 round trips; the batching form
     (2000 mixed images) with the tuner's schedule; the differentiation form
     (64 x 1024^2 FP32): statistics pass, forward with P, adjoint backward and
-    the 200-step tuning loop.  Every figure is a HIP-graph replay average."""
+    the 200-step tuning loop.  Figures are averages over direct launches; the
+    batching form is also timed as a HIP-graph replay, its intended use."""
     from paper_1512_02951_amd import softmask as sm
     from paper_1512_02951_amd.batch import Batch
     status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -191,7 +199,7 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
             for x, c, fr, y in zip(xs, ctrs, frs, ys):
                 sf.frag_image(x, mask, key, c, precision=prec, out=fr, status=status)
                 sf.defrag_image(fr, key, c, out=y, status=status)
-        g = capture(torch, rt)
+        g = _Eager(rt)
         ms = time_graphs(torch, [g], steps, warmup)
         assert int(status.item()) == 0 and all(torch.equal(x, y) for x, y in zip(xs, ys))
         lp = prec != "fp32"
@@ -218,6 +226,7 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
     b.frag(status=status)
     gb = capture(torch, brt)
     ms = time_graphs(torch, [gb], max(steps // 4, 3), warmup)
+    ms_direct = time_graphs(torch, [_Eager(brt)], max(steps // 4, 3), warmup)
     assert int(status.item()) == 0 and all(torch.equal(x, y) for x, y in zip(imgs, b.restored))
     samples = sum(x.numel() for x in imgs)
     nbytes = 2 * sum(_bytes_plain(h, w, c, kk + 1) for (h, w, c, kk) in specs)
@@ -225,7 +234,8 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
                                    "one persistent kernel per direction, HIP graph",
                        "tiles_per_grab": tuning[0], "workgroups_per_cu": tuning[1],
                        "ms_per_step": round(ms, 4), "MP/s": round(samples / 1e6 / (ms * 1e-3), 1),
-                       "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+                       "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                       "direct_launch_ms_per_step": round(ms_direct, 4)}
     del imgs, b, gb
 
     # ---- differentiation form
@@ -240,8 +250,7 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
     for name, fn, bps in (("statistics", lambda: sm.forward(x, l, public=False), 4),
                           ("forward_with_P", lambda: sm.forward(x, l), 8),
                           ("adjoint_backward", lambda: sm.backward(x, G, l), 8)):
-        g = capture(torch, fn)
-        ms = time_graphs(torch, [g], steps, warmup)
+        ms = time_graphs(torch, [_Eager(fn)], steps, warmup)
         res[name] = {"ms": round(ms, 4), "GB/s": round(nsamp * bps / (ms * 1e-3) / 1e9, 1)}
     _, stats = sm.forward(x, l, public=False)
     lt = l.clone()
@@ -252,7 +261,7 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
     tune_args = (ctypes.c_void_p(stats.data_ptr()), B, Hs, Ws, sm.LAMBDA, sm.BUDGET, 200, 0.05,
                  ctypes.c_void_p(lt.data_ptr()), ctypes.c_void_p(trace.data_ptr()), ctypes.c_void_p(mask_t.data_ptr()),
                  6)
-    gt = capture(torch, lambda: sf.check(L.sf_softmask_tune(*tune_args, sf._stream(None))))
+    gt = _Eager(lambda: sf.check(L.sf_softmask_tune(*tune_args, sf._stream(None))))
     res["tune_200_adam_steps"] = {"ms": round(time_graphs(torch, [gt], 5, 1), 4)}
     out["differentiation"] = {"workload": "64 x 1024^2 FP32 in [0, 1], soft mask over 64 frequencies", **res}
     return out
@@ -269,7 +278,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the companion figures of the three forms")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference kernel for HBM byte counters)")
-    ap.add_argument("--eager", action="store_true", help="launch directly instead of replaying HIP graphs")
+    ap.add_argument("--graph", action="store_true", help="replay one HIP graph per step instead of direct launches")
+    ap.add_argument("--eager", action="store_true", help="direct launches (the default; kept for old command lines)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
@@ -294,7 +304,7 @@ def main():
     sets = make_sets(sf, synth, torch, dev, args.sets, mask, key)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
-    ms, frag_ms, defrag_ms = measure(sf, torch, sets, mask, key, status, args.steps, args.warmup, args.eager)
+    ms, frag_ms, defrag_ms = measure(sf, torch, sets, mask, key, status, args.steps, args.warmup, args.graph)
     # every buffer set once more (the timed loop may not reach all of them)
     for x, fr, y, c0 in sets:
         sf.frag_image(x, mask, key, c0, out=fr, status=status)
@@ -324,7 +334,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "4096x4096 RGB planar uint8, DC+5 AC private (int16, AES-128-CTR), 58 FP32 public "
                                "coefficients per 8x8 block, bit-exact round trip", "images_per_step": 1,
-                   "buffer_sets": len(sets), "launch": "direct launches" if args.eager else "HIP graph per step (frag_image + defrag_image)"},
+                   "buffer_sets": len(sets), "launch": "HIP graph per step (frag_image + defrag_image)" if args.graph
+                   else "frag_image + defrag_image launched directly on one stream"},
         "round_trip_GBps": round(round_trip_gbs, 1),
         "hbm_frac_round_trip": round(round_trip_gbs / HBM_PEAK_GBS, 4),
         "frag_ms": round(frag_ms, 5),

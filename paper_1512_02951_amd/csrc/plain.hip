@@ -9,7 +9,7 @@
 namespace sf {
 namespace {
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 2;  // 2 waves per workgroup measured best (1, 2, 4, 8 tried)
 constexpr int kThreads = 64 * kWaves;
 
 struct FragKernelArgs {
@@ -133,13 +133,13 @@ __global__ __launch_bounds__(kThreads, SF_DEFRAG_WAVES_PER_EU) void defrag_fp32_
 
 uint32_t lds_priv_bytes(const Geom &g) { return (2u * g.npriv * 64u + 15u) & ~15u; }
 
-int grid_for(const DeviceState &ds, const void *kernel, size_t lds, uint32_t ntiles) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  const uint32_t need = (ntiles + kWaves - 1) / kWaves;
-  const uint32_t cap = (uint32_t)ds.num_cu * (uint32_t)per_cu;
-  return (int)(need < cap ? need : cap);
+// One tile per wave: the hardware dispatcher keeps every SIMD at its
+// occupancy limit and refills it as waves finish, which measured faster than
+// resident waves looping over tiles (the kernels still loop if the grid is
+// ever capped).  Beyond 2^31 - 1 workgroups the grid is capped at that.
+int grid_for(const DeviceState &, const void *, size_t, uint32_t ntiles) {
+  const uint64_t need = ((uint64_t)ntiles + kWaves - 1) / kWaves;
+  return (int)(need < 0x7fffffffu ? need : 0x7fffffffu);
 }
 
 template <class MP, bool kQ2Mfma>
