@@ -215,20 +215,23 @@ __device__ __forceinline__ Q2Operands q2_operands(const uint32_t *q2, int n, int
   return o;
 }
 
-// xs: the lane's block as signed bytes (samples - 128); Qs: the lane's B
-// operand (kept in LDS by the kernel).  Leaves acc of AC
-// index a for block `lane` at stage + a * kQ2AccStride + 4 lane; the caller
-// issues wave_lds_sync() before reading it.
-__device__ __forceinline__ void q2_mfma(const uint32_t (&xs)[16], int lane, uint8_t *stage, const Q2Operands &Qs) {
+// The three steps of q2_mfma, for callers that read more of the staged
+// pixels between them: (1) the lane's block (signed bytes) into its 80-byte
+// LDS row; (2) after wave_lds_sync(), the lane's A operands; (3) after a
+// second wave_lds_sync(), the products, written over the staged pixels.
+__device__ __forceinline__ void q2_stage_pixels(const uint32_t (&xs)[16], int lane, uint8_t *stage) {
   uint4 *own = reinterpret_cast<uint4 *>(stage + lane * kQ2PixStride);
 #pragma unroll
   for (int j = 0; j < 4; ++j) own[j] = make_uint4(xs[4 * j], xs[4 * j + 1], xs[4 * j + 2], xs[4 * j + 3]);
-  wave_lds_sync();
-  q2v4 A[4];
+}
+
+__device__ __forceinline__ void q2_read_a(int lane, const uint8_t *stage, q2v4 (&A)[4]) {
   const uint8_t *src = stage + (lane & 15) * kQ2PixStride + 16 * (lane >> 4);
 #pragma unroll
   for (int bg = 0; bg < 4; ++bg) A[bg] = *reinterpret_cast<const q2v4 *>(src + 16 * bg * kQ2PixStride);
-  wave_lds_sync();
+}
+
+__device__ __forceinline__ void q2_products(const q2v4 (&A)[4], int lane, uint8_t *stage, const Q2Operands &Qs) {
   uint8_t *dst = stage + (lane & 15) * kQ2AccStride + 16 * (lane >> 4);
   const Q2Operands Q = Qs;  // from LDS: not held in registers between tiles
 #pragma unroll
@@ -242,6 +245,19 @@ __device__ __forceinline__ void q2_mfma(const uint32_t (&xs)[16], int lane, uint
     c = (q2v4)((q2u4)c + Q.bias);
     *reinterpret_cast<q2v4 *>(dst + 64 * bg) = c;
   }
+}
+
+// xs: the lane's block as signed bytes (samples - 128); Qs: the lane's B
+// operand (kept in LDS by the kernel).  Leaves acc of AC index a for block
+// `lane` at stage + a * kQ2AccStride + 4 lane; the caller issues
+// wave_lds_sync() before reading it.
+__device__ __forceinline__ void q2_mfma(const uint32_t (&xs)[16], int lane, uint8_t *stage, const Q2Operands &Qs) {
+  q2_stage_pixels(xs, lane, stage);
+  wave_lds_sync();
+  q2v4 A[4];
+  q2_read_a(lane, stage, A);
+  wave_lds_sync();
+  q2_products(A, lane, stage, Qs);
 }
 
 __device__ __forceinline__ int32_t q2_mfma_acc(const uint8_t *stage, uint32_t a, int lane) {

@@ -454,11 +454,31 @@ int sm_check(uint32_t B, uint32_t H, uint32_t W) {
   return SF_OK;
 }
 
+// Many parts per output: one workgroup per output, 256 threads summing
+// strided parts in a fixed order, then a fixed LDS tree (deterministic).
+__global__ __launch_bounds__(256) void sm_reduce_wide_kernel(const double *partials, uint32_t parts, uint32_t kN,
+                                                              double *out) {
+  __shared__ double s[256];
+  const uint32_t o = blockIdx.x, i = o / kN, k = o - i * kN;
+  double v = 0.0;
+  for (uint32_t j = threadIdx.x; j < parts; j += 256) v += partials[((size_t)i * parts + j) * kN + k];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (uint32_t w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[o] = s[0];
+}
+
 int sm_launch_reduce(const double *partials, uint32_t items, uint32_t parts, uint32_t kN, double *out,
                      hipStream_t stream) {
   const uint32_t total = items * kN;
-  hipLaunchKernelGGL(sm_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, stream, partials, items, parts, kN,
-                     out);
+  if (parts > 64)
+    hipLaunchKernelGGL(sm_reduce_wide_kernel, dim3(total), dim3(256), 0, stream, partials, parts, kN, out);
+  else
+    hipLaunchKernelGGL(sm_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, stream, partials, items, parts,
+                       kN, out);
   return SF_OK;
 }
 
