@@ -407,17 +407,20 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void frag_lp_kernel(
   const uint32_t stride = gridDim.x * kWaves;
   uint32_t rflag = 0;
 
-  for (uint32_t t = blockIdx.x * kWaves + wave; t < g.ntiles; t += stride) {
-    const TileLane L = tile_lane(g, t, lane);
+  uint32_t t = blockIdx.x * kWaves + wave;
+  TileLane Lnext = tile_lane(g, t < g.ntiles ? t : 0u, lane);
+  uint32_t xs[16];
+  if (t < g.ntiles) load_block(g, Lnext, xs);
+  for (; t < g.ntiles; t += stride) {
+    const TileLane L = Lnext;
     const uint64_t b0 = L.b0;
     const uint32_t ntb = L.nt;
+    const uint32_t tn = t + stride;
 
     // ---- the lane's block: exact sum, staged for the quantiser and for the
     // forward-transform operands (lane half h: rows 2s + h of block jb)
     uint2 prow[2][4];
     {
-      uint32_t xs[16];
-      load_block(g, L, xs);
       uint32_t S = 0;
 #pragma unroll
       for (int w = 0; w < 16; ++w) S = __builtin_amdgcn_udot4(xs[w], 0x01010101u, S, false);
@@ -449,6 +452,11 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void frag_lp_kernel(
         else if constexpr (kQ2Mfma) q = q2_round(q2_mfma_acc(stage, i - dc_priv, lane));
         else q = q2_round(q2_acc(xs, q2 + n * kQ2RowWords));
         if (L.valid) *reinterpret_cast<int16_t *>(lp + 2u * (i * ntb + lane)) = (int16_t)q;
+      }
+      // the next tile's pixels, in flight during the transforms of this one
+      if (tn < g.ntiles) {
+        Lnext = tile_lane(g, tn, lane);
+        load_block(g, Lnext, xs);
       }
     }
     wave_lds_sync();
@@ -578,6 +586,13 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void defrag_lp_kerne
       const uint32_t jb = 32u * nt + jl;
       const bool bv = jb < ntb;
       const uint32_t borg = bv ? block_origin(g, (uint32_t)b0 + jb) : 0u;
+      // this half's residual words, in flight during the operand gathering and
+      // the inverse transform
+      uint32_t rw[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        rw[r] = bv ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(a.resid + borg + (size_t)r * g.W + 4u * h))
+                   : 0u;
       uint4 chi[4], clo[4];
       lp_inverse_operands<BF, MP>(mask, h, jb, bv, ntb, lp,
                                   [&](int, int, uint32_t rank) {
@@ -592,9 +607,8 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void defrag_lp_kerne
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const size_t off = borg + (size_t)(4 * mt + q4) * g.W + 4u * h;
-          const uint32_t rw = bv ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(a.resid + off)) : 0u;
           // rec + r is the sample itself, in [0, 255]: byte-wise addition
-          const uint32_t ow = bytes_add(rec_word(y[mt], q4), rw);
+          const uint32_t ow = bytes_add(rec_word(y[mt], q4), rw[4 * mt + q4]);
           if (bv) __builtin_nontemporal_store(ow, reinterpret_cast<uint32_t *>(a.pix_out + off));
         }
       if (nt == 0) {
