@@ -169,7 +169,12 @@ __device__ __forceinline__ void dispatch_mask(uint64_t mask, F &&f) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void frag_batch_kernel(BatchArgs a) {
+// Per-wave LDS of the batched frag: private bytes, the quantiser stage, and
+// the quantiser's B operand for the mask of the image in hand (recomputed
+// when the wave moves to an image with another mask).
+constexpr uint32_t kBatchQ2Bytes = kQ2StageBytes + 64u * sizeof(Q2Operands);
+
+__global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
@@ -178,8 +183,13 @@ __global__ __launch_bounds__(kThreads) void frag_batch_kernel(BatchArgs a) {
   const uint32_t enc = hd->enc;
   if (enc) aes_load_tables(s_aes, a.aes_t0, hd->key, threadIdx.x, kThreads);
   __syncthreads();
-  uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
-  batch_loop(a.ws, a.n, 0, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) {
+  uint8_t *lp = s_dyn + wave * (a.lds_priv_bytes + kBatchQ2Bytes);
+  uint8_t *stage = lp + a.lds_priv_bytes;
+  Q2Operands *wq = reinterpret_cast<Q2Operands *>(stage + kQ2StageBytes);
+  uint64_t qmask = 0;  // mask whose operands wq holds (masks are never 0)
+  // the body must be inlined: its buffer resources and table pointers live in
+  // scalar registers, which an outlined call could not guarantee
+  batch_loop(a.ws, a.n, 0, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) __attribute__((always_inline)) {
     FragOut o;
     o.pub = d.pub;
     o.priv = d.priv;
@@ -190,13 +200,25 @@ __global__ __launch_bounds__(kThreads) void frag_batch_kernel(BatchArgs a) {
     const TileLane L = tile_lane(d.g, t, lane);
     uint32_t xs[16];
     load_block(d.g, L, xs);
-    dispatch_mask(d.g.mask, [&](auto mp) {
-      frag_tile<decltype(mp)>(d.g, o, t, L, xs, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K);
+    const bool mfma_q2 = __builtin_popcountll(d.g.mask & ~1ull) <= kQ2MfmaMaxAc;
+    dispatch_mask(d.g.mask, [&](auto mp) __attribute__((always_inline)) {
+      using MP = decltype(mp);
+      if (mfma_q2) {
+        if (d.g.mask != qmask) {
+          wave_lds_sync();
+          wq[lane] = q2_operands(a.q2, private_ac<MP>(d.g.mask, lane & 15), lane);
+          wave_lds_sync();
+          qmask = d.g.mask;
+        }
+        frag_tile<MP, true>(d.g, o, t, L, xs, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K, stage, &wq[lane]);
+      } else {
+        frag_tile<MP, false>(d.g, o, t, L, xs, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K);
+      }
     });
   });
 }
 
-__global__ __launch_bounds__(kThreads) void defrag_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kThreads, 3) void defrag_batch_kernel(BatchArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
@@ -206,14 +228,14 @@ __global__ __launch_bounds__(kThreads) void defrag_batch_kernel(BatchArgs a) {
   if (enc) aes_load_tables(s_aes, a.aes_t0, hd->key, threadIdx.x, kThreads);
   __syncthreads();
   uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
-  batch_loop(a.ws, a.n, 1, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) {
+  batch_loop(a.ws, a.n, 1, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) __attribute__((always_inline)) {
     DefragIn in;
     in.pix_out = d.out;
     in.pub = d.pub;
     in.priv = d.priv;
     in.exc = d.exc;
     const TileLane L = tile_lane(d.g, t, lane);
-    dispatch_mask(d.g.mask, [&](auto mp) {
+    dispatch_mask(d.g.mask, [&](auto mp) __attribute__((always_inline)) {
       defrag_tile<decltype(mp)>(d.g, in, t, L, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K);
     });
   });
@@ -251,7 +273,7 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   a.cert_thr = cert_threshold();
   a.K = host_tables().dct;
   if (a.tiles_per_grab > 1024) return fail(SF_ERANGE, "tiles_per_grab must be at most 1024");
-  const size_t lds = (size_t)kWaves * a.lds_priv_bytes;
+  const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + (which == 0 ? kBatchQ2Bytes : 0u));
   const void *fn = which == 0 ? (const void *)frag_batch_kernel : (const void *)defrag_batch_kernel;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
