@@ -173,12 +173,12 @@ def _bytes_plain(H, W, C, npriv, pub_elt=4, residual=False):
 
 
 def measure_forms(sf, torch, synth, dev, steps, warmup):
-    """Companion figures for the three forms, each on its own workload (these
+    """Companion figures for the other forms, each on its own workload (these
     are not the headline number): the precision form (16 images 8192^2 gray,
     DC + 9 AC private) as FP32 vs fp16 vs bf16 round trips; the batching form
     (2000 mixed images) with the tuner's schedule; the differentiation form
     (64 x 1024^2 FP32): statistics pass, forward with P, adjoint backward and
-    the 200-step tuning loop.  Figures are averages over direct launches; the
+    the 200-step tuning loop; the wavelet form on the 4096^2 RGB image.  Figures are averages over direct launches; the
     batching form is also timed as a HIP-graph replay, its intended use."""
     from paper_1512_02951_amd import softmask as sm
     from paper_1512_02951_amd.batch import Batch
@@ -264,6 +264,31 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
     gt = _Eager(lambda: sf.check(L.sf_softmask_tune(*tune_args, sf._stream(None))))
     res["tune_200_adam_steps"] = {"ms": round(time_graphs(torch, [gt], 5, 1), 4)}
     out["differentiation"] = {"workload": "64 x 1024^2 FP32 in [0, 1], soft mask over 64 frequencies", **res}
+    del x, G, stats
+
+    # ---- wavelet form (LeGall 5/3, two levels per 8x8 block, 2x2 LL2 private)
+    from paper_1512_02951_amd import dwt
+    S, C = 4096, 3
+    wkey = synth.aes_key(2)
+    wx = [synth.image(S, S, C, 2, i, device=dev) for i in range(2)]
+    wc = [synth.ctr0(2, i) for i in range(2)]
+    wfr = [dwt.dwt_frag_image(x, wkey, c) for x, c in zip(wx, wc)]
+    wy = [torch.empty_like(x) for x in wx]
+    it = [0]
+
+    def wrt():
+        i = it[0] % 2
+        it[0] += 1
+        dwt.dwt_frag_image(wx[i], wkey, wc[i], out=wfr[i])
+        dwt.dwt_defrag_image(wfr[i], wkey, wc[i], out=wy[i])
+    ms = time_graphs(torch, [_Eager(wrt)], steps, warmup)
+    assert all(torch.equal(x, y) for x, y in zip(wx, wy))
+    nsamp = C * S * S
+    # frag: 1 B in, 2 B out per sample; defrag: 2 B in, 1 B out
+    out["wavelet"] = {"workload": "4096^2 RGB uint8, LeGall 5/3 two levels per 8x8 block, LL2 (4 of 64) private, "
+                                  "round trip (exact)",
+                      "ms_per_step": round(ms, 4), "MP/s": round(nsamp / 1e6 / (ms * 1e-3), 1),
+                      "GB/s": round(6 * nsamp / (ms * 1e-3) / 1e9, 1)}
     return out
 
 
@@ -282,7 +307,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="direct launches (the default; kept for old command lines)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU; runs over several GPUs are not supported (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -226,6 +226,34 @@ int sf_defrag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint
 int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *best_ms, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Wavelet variant (Sec. 6.8-6.9, Eqs. (1)-(2), Fig. 18): every 8x8 block of
+ * a planar uint8 image (samples read as x - 128, Sec. 6.9.4) goes through two
+ * levels of the LeGall 5/3 integer lifting (rows, then columns; the second
+ * level on the 4x4 low-low quarter; whole-sample symmetric extension).  The
+ * 2x2 second-level low-low corner is the private fragment (Sec. 6.9.3: 4 of
+ * 64 coefficients), int16 little endian, encrypted with AES-128-CTR as one
+ * byte stream (as frag_image; aes may be NULL for plaintext); the other 60
+ * coefficients, in row-major order of their positions, are the public
+ * fragment, int16.  Both fragments use the tile-interleaved layout of
+ * frag_image with P = 4 (private) and P = 60 (public) values per block.
+ * Integer lifting is exactly invertible: defragmentation restores every
+ * sample with no exception list or residual.  Buffers: pixels 8-byte
+ * aligned, fragments 16-byte aligned, device memory owned by the caller;
+ * errors as for frag_image.  Any byte data can be processed by viewing it as
+ * a gray image of width W (Sec. 6.9.3, data-agnostic chunking).
+ * ------------------------------------------------------------------- */
+
+/* Host only: public and private fragment bytes of an H x W x C image. */
+int sf_dwt_fragment_sizes(uint32_t height, uint32_t width, uint32_t channels, size_t *public_bytes,
+                          size_t *private_bytes);
+
+int dwt_frag_image(uint32_t height, uint32_t width, uint32_t channels, const uint8_t *d_pixels, int16_t *d_public,
+                   uint8_t *d_private, const sf_aes_ctr *aes, void *stream);
+
+int dwt_defrag_image(uint32_t height, uint32_t width, uint32_t channels, const int16_t *d_public,
+                     const uint8_t *d_private, const sf_aes_ctr *aes, uint8_t *d_pixels, void *stream);
+
+/* ---------------------------------------------------------------------
  * Differentiation form: a soft per-frequency selection mask
  * m_n = sigmoid(l_n) over the 64 natural frequencies n = 8u + v, and the
  * public image it leaves, P = IDCT(DCT(x) * (1 - m)) per 8x8 block (the

@@ -269,6 +269,67 @@ int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *bes
   return rc;
 }
 
+// ---- wavelet variant
+static int dwt_geom(uint32_t H, uint32_t W, uint32_t C, Geom *g) {
+  if (H == 0 || W == 0 || H % 8 || W % 8) return fail(SF_ESHAPE, "height and width must be positive multiples of 8");
+  if (C == 0) return fail(SF_ESHAPE, "channels must be >= 1");
+  const uint64_t samples = (uint64_t)H * W * C;
+  if (samples >= (1ull << 32)) return fail(SF_ESHAPE, "image must hold fewer than 2^32 samples");
+  g->H = H;
+  g->W = W;
+  g->C = C;
+  g->Bx = W / 8;
+  g->By = H / 8;
+  g->nb = samples / 64;
+  g->ntiles = (uint32_t)((g->nb + 63) / 64);
+  g->mask = 0;
+  g->npriv = 4;
+  g->npub = 60;
+  g->precision = SF_FP32;
+  return SF_OK;
+}
+
+int sf_dwt_fragment_sizes(uint32_t H, uint32_t W, uint32_t C, size_t *public_bytes, size_t *private_bytes) {
+  Geom g;
+  int rc = dwt_geom(H, W, C, &g);
+  if (rc) return rc;
+  if (public_bytes) *public_bytes = (size_t)g.nb * 60u * 2u;
+  if (private_bytes) *private_bytes = (size_t)g.nb * 4u * 2u;
+  return SF_OK;
+}
+
+int dwt_frag_image(uint32_t H, uint32_t W, uint32_t C, const uint8_t *d_pixels, int16_t *d_public,
+                   uint8_t *d_private, const sf_aes_ctr *aes, void *stream) {
+  Geom g;
+  int rc = dwt_geom(H, W, C, &g);
+  if (rc) return rc;
+  if (!d_pixels || !d_public || !d_private) return fail(SF_EINVAL, "NULL buffer");
+  if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  AesArgs a;
+  make_aes_args(aes, &a);
+  rc = launch_dwt_frag(*ds, g, d_pixels, d_public, d_private, a, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int dwt_defrag_image(uint32_t H, uint32_t W, uint32_t C, const int16_t *d_public, const uint8_t *d_private,
+                     const sf_aes_ctr *aes, uint8_t *d_pixels, void *stream) {
+  Geom g;
+  int rc = dwt_geom(H, W, C, &g);
+  if (rc) return rc;
+  if (!d_pixels || !d_public || !d_private) return fail(SF_EINVAL, "NULL buffer");
+  if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  AesArgs a;
+  make_aes_args(aes, &a);
+  rc = launch_dwt_defrag(*ds, g, d_public, d_private, a, d_pixels, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
 // ---- differentiation form
 static int sm_ptrs(const void *a, const void *b) {
   if (!a || !b) return fail(SF_EINVAL, "NULL buffer");

@@ -100,6 +100,12 @@ int batch_run(const DeviceState &ds, const void *d_ws, int which, const sf_batch
               hipStream_t stream);
 int batch_autotune(const DeviceState &ds, const void *d_ws, sf_batch_tuning *best, float *best_ms,
                    hipStream_t stream);
+// Wavelet variant (dwt.hip).
+int launch_dwt_frag(const DeviceState &ds, const Geom &g, const uint8_t *pix, int16_t *pub, uint8_t *priv,
+                    const AesArgs &aes, hipStream_t stream);
+int launch_dwt_defrag(const DeviceState &ds, const Geom &g, const int16_t *pub, const uint8_t *priv,
+                      const AesArgs &aes, uint8_t *pix, hipStream_t stream);
+
 // Differentiation form (softmask.hip).
 size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, uint32_t W);
 int softmask_forward(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W, const float *logits,

@@ -34,6 +34,7 @@ Workloads
 4: 2000 images, width/height log-uniform in [256, 4096] rounded to x8,
    1 or 3 channels (p = 1/2), k from {1, 2, 5, 9} (batched form)
 5: 64 grayscale 1024x1024 images as float32 pixel/255 (soft-mask form)
+The wavelet form runs on workload 2's images and key.
 """
 from __future__ import annotations
 
