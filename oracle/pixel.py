@@ -1,0 +1,203 @@
+"""Plain CPU oracle of the pixel-domain fragment formats -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module; it shares no code with the GPU library.
+
+The report's own storage formats (Sec. 6.3.1-6.3.2, Sec. 6.4.3, Figs. 6-8,
+Table 5), numpy integer arithmetic plus hashlib's SHA-512:
+
+* private part: the integer private coefficients (rule Q2 of the DCT form,
+  ``oracle.q2_blocks``) in zigzag order, each stored in 11 bits (Sec. 6.4.3):
+  DC unsigned (0..2040), AC as a sign bit above a 10-bit magnitude.  The 11-bit
+  fields of the blocks of a 64-block tile follow each other in one little-endian
+  bit stream (field j of block i of the tile at bit 11 (i P + j), P fields per
+  block); a full tile takes 88 P bytes and starts on a 16-byte boundary
+  (stride 16 ceil(88 P / 16)), the last tile takes ceil(11 P n_t / 8) bytes.
+  The whole private byte string is AES-128-CTR encrypted as in the DCT form
+  (the counter of tile t starts at block t * stride / 16).
+* public part: one byte per sample, image layout.  The report stores the
+  inverse DCT of the remaining coefficients (private ones set to zero) as
+  bytes.  Here that image is represented by P = (x - R) mod 256, where
+  R = rhe(sum_j q_j Bi[n_j][p] / 2^16), Bi = rhe(2^16 B), is the integer
+  inverse of the private integers: since x = IDCT(private part) +
+  IDCT(rest) exactly, P differs from the inverse transform of the rest only by
+  how far R is from IDCT(private part) (a bound is checked in the tests), and
+  (R + P) mod 256 gives x back exactly.
+* strong level (Sec. 6.3.2, Fig. 8): the 64 public bytes of a block are
+  XORed with the SHA-512 digest (FIPS 180-4) of the block's private integers,
+  int16 little-endian in zigzag order; digest byte p masks sample p = 8y + x.
+"""
+from __future__ import annotations
+
+import hashlib
+
+import numpy as np
+
+from . import basis, blocks_of, ctr_xor, popcount, q2_blocks, zigzag, _planes
+
+FIELD_BITS = 11
+INV_SHIFT = 16
+
+
+def inv_table() -> np.ndarray:
+    """Bi[n][p] = round_half_even(2^16 B[n][p]) as int64 (64 x 64)."""
+    s = basis() * (1 << INV_SHIFT)
+    # every entry is far from a rounding tie, so FP64 decides it exactly
+    assert np.abs(s - np.floor(s) - 0.5).min() > 1e-6
+    return np.rint(s).astype(np.int64)
+
+
+def rhe_shift(a: np.ndarray, s: int) -> np.ndarray:
+    """round_half_even(a / 2^s) for int64 arrays."""
+    a = np.asarray(a, np.int64)
+    fl = a >> s                                  # floor
+    rem = a - (fl << s)                          # 0 .. 2^s - 1
+    half = 1 << (s - 1)
+    up = (rem > half) | ((rem == half) & ((fl & 1) == 1))
+    return fl + up.astype(np.int64)
+
+
+def private_positions(mask: int):
+    """(zigzag positions, natural indices) of the private coefficients."""
+    zz = zigzag()
+    zpos = [z for z in range(64) if (mask >> z) & 1]
+    return zpos, [int(zz[z]) for z in zpos]
+
+
+def private_ints(pix: np.ndarray, mask: int) -> np.ndarray:
+    """(nb, P) int64 private integers in zigzag order (rule Q2)."""
+    _, nat = private_positions(mask)
+    return q2_blocks(pix, nat).astype(np.int64)
+
+
+def recon_private(q: np.ndarray, mask: int) -> np.ndarray:
+    """R: (nb, 64) integer inverse of the private integers."""
+    _, nat = private_positions(mask)
+    Bi = inv_table()
+    acc = np.asarray(q, np.int64) @ Bi[nat]       # (nb, 64), exact in int64
+    return rhe_shift(acc, INV_SHIFT)
+
+
+def strong_keystream(q: np.ndarray) -> np.ndarray:
+    """(nb, 64) uint8: SHA-512 of each block's private integers (int16 LE)."""
+    q = np.asarray(q, np.int64)
+    assert np.abs(q).max(initial=0) < 2 ** 15
+    msgs = q.astype("<i2")
+    out = np.empty((q.shape[0], 64), np.uint8)
+    for b in range(q.shape[0]):
+        out[b] = np.frombuffer(hashlib.sha512(msgs[b].tobytes()).digest(), np.uint8)
+    return out
+
+
+def _fields(q: np.ndarray, mask: int) -> np.ndarray:
+    zpos, _ = private_positions(mask)
+    q = np.asarray(q, np.int64)
+    f = np.empty(q.shape, np.int64)
+    for j, z in enumerate(zpos):
+        if z == 0:
+            assert q[:, j].min(initial=0) >= 0 and q[:, j].max(initial=0) < 2 ** FIELD_BITS
+            f[:, j] = q[:, j]
+        else:
+            mag = np.abs(q[:, j])
+            assert mag.max(initial=0) < 2 ** (FIELD_BITS - 1)
+            f[:, j] = mag | ((q[:, j] < 0).astype(np.int64) << (FIELD_BITS - 1))
+    return f
+
+
+def _unfields(f: np.ndarray, mask: int) -> np.ndarray:
+    zpos, _ = private_positions(mask)
+    q = np.empty(f.shape, np.int64)
+    for j, z in enumerate(zpos):
+        if z == 0:
+            q[:, j] = f[:, j]
+        else:
+            mag = f[:, j] & ((1 << (FIELD_BITS - 1)) - 1)
+            q[:, j] = np.where((f[:, j] >> (FIELD_BITS - 1)) & 1, -mag, mag)
+    return q
+
+
+def tile_stride(P: int) -> int:
+    return 16 * ((88 * P + 15) // 16)
+
+
+def private_bytes(nb: int, P: int) -> int:
+    if nb == 0:
+        return 0
+    nt_last = nb - 64 * ((nb - 1) // 64)
+    return ((nb - 1) // 64) * tile_stride(P) + (FIELD_BITS * P * nt_last + 7) // 8
+
+
+def pack11(q: np.ndarray, mask: int) -> np.ndarray:
+    """(nb, P) private integers -> packed private bytes (tile streams)."""
+    f = _fields(q, mask)
+    nb, P = f.shape
+    out = np.zeros(private_bytes(nb, P), np.uint8)
+    st = tile_stride(P)
+    for t0 in range(0, nb, 64):
+        ft = f[t0:t0 + 64]
+        bits = ((ft[..., None] >> np.arange(FIELD_BITS)) & 1).astype(np.uint8).reshape(-1)
+        by = np.packbits(bits, bitorder="little")
+        base = (t0 // 64) * st
+        out[base:base + by.size] = by
+    return out
+
+
+def unpack11(data: np.ndarray, nb: int, mask: int) -> np.ndarray:
+    """Inverse of pack11."""
+    P = popcount(mask)
+    data = np.asarray(data, np.uint8)
+    st = tile_stride(P)
+    f = np.zeros((nb, P), np.int64)
+    for t0 in range(0, nb, 64):
+        nt = min(64, nb - t0)
+        nbits = FIELD_BITS * P * nt
+        base = (t0 // 64) * st
+        bits = np.unpackbits(data[base:base + (nbits + 7) // 8], bitorder="little")[:nbits]
+        f[t0:t0 + nt] = (bits.reshape(nt, P, FIELD_BITS).astype(np.int64) << np.arange(FIELD_BITS)).sum(-1)
+    return _unfields(f, mask)
+
+
+def _unblocks(v: np.ndarray, shape) -> np.ndarray:
+    C, H, W = shape
+    return v.reshape(C, H // 8, W // 8, 8, 8).transpose(0, 1, 3, 2, 4).reshape(C, H, W)
+
+
+def frag(pix: np.ndarray, mask: int, strong: bool = False, key: bytes | None = None, ctr0: bytes | None = None):
+    """Returns dict: public (C, H, W) uint8, private (packed plain bytes),
+    cipher (bytes or None), q (nb, P) private integers."""
+    pix = _planes(pix)
+    blk = blocks_of(pix).astype(np.int64)
+    q = private_ints(pix, mask)
+    R = recon_private(q, mask)
+    pub = ((blk - R) & 0xFF).astype(np.uint8)
+    if strong:
+        pub ^= strong_keystream(q)
+    plain = pack11(q, mask)
+    out = {"public": _unblocks(pub, pix.shape), "private": plain, "cipher": None, "q": q}
+    if key is not None:
+        out["cipher"] = ctr_xor(key, ctr0 if ctr0 is not None else bytes(16), plain)
+    return out
+
+
+def defrag(shape, mask: int, public: np.ndarray, private: np.ndarray | None = None, strong: bool = False,
+           key: bytes | None = None, ctr0: bytes | None = None, cipher: np.ndarray | None = None) -> np.ndarray:
+    C, H, W = shape
+    nb = C * (H // 8) * (W // 8)
+    if cipher is not None:
+        private = ctr_xor(key, ctr0 if ctr0 is not None else bytes(16), np.asarray(cipher, np.uint8))
+    q = unpack11(private, nb, mask)
+    pub = blocks_of(np.asarray(public, np.uint8).reshape(C, H, W)).copy()
+    if strong:
+        pub ^= strong_keystream(q)
+    x = (recon_private(q, mask) + pub.astype(np.int64)) & 0xFF
+    return _unblocks(x.astype(np.uint8), shape)
+
+
+def fragment_bytes(C: int, H: int, W: int, mask: int):
+    """(public_bytes, private_bytes)."""
+    nb = C * (H // 8) * (W // 8)
+    return C * H * W, private_bytes(nb, popcount(mask))
+
+
+__all__ = ["inv_table", "rhe_shift", "private_positions", "private_ints", "recon_private", "strong_keystream",
+           "tile_stride", "private_bytes", "pack11", "unpack11", "frag", "defrag", "fragment_bytes"]
