@@ -289,6 +289,33 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
                                   "round trip (exact)",
                       "ms_per_step": round(ms, 4), "MP/s": round(nsamp / 1e6 / (ms * 1e-3), 1),
                       "GB/s": round(6 * nsamp / (ms * 1e-3) / 1e9, 1)}
+    del wx, wy, wfr
+
+    # ---- pixel-domain formats (11-bit private fields, byte public), both levels
+    from paper_1512_02951_amd import pixel
+    pk = sf.prefix_mask(5)
+    px_x = [synth.image(S, S, C, 2, i, device=dev) for i in range(2)]
+    for strong in (False, True):
+        pfr = [pixel.pixel_frag_image(x, pk, strong, wkey, c) for x, c in zip(px_x, wc)]
+        py = [torch.empty_like(x) for x in px_x]
+        pit = [0]
+
+        def prt(pfr=pfr, py=py, pit=pit, strong=strong):
+            i = pit[0] % 2
+            pit[0] += 1
+            pixel.pixel_frag_image(px_x[i], pk, strong, wkey, wc[i], out=pfr[i])
+            pixel.pixel_defrag_image(pfr[i], wkey, wc[i], out=py[i])
+        ms = time_graphs(torch, [_Eager(prt)], steps, warmup)
+        assert all(torch.equal(x, y) for x, y in zip(px_x, py))
+        _, qb = pixel.fragment_sizes(S, S, C, pk)
+        nbytes = 2 * (2 * nsamp + qb)  # each direction: image + public bytes + packed private bytes
+        out["pixel_strong" if strong else "pixel_first"] = {
+            "workload": "4096^2 RGB uint8, DC+5 AC private in 11-bit fields (AES-128-CTR), public bytes in the pixel "
+                        "domain" + (", XOR SHA-512 of the private integers (strong level)" if strong else "")
+                        + ", round trip (exact)",
+            "ms_per_step": round(ms, 4), "MP/s": round(nsamp / 1e6 / (ms * 1e-3), 1),
+            "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+        del pfr, py
     return out
 
 

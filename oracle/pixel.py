@@ -18,8 +18,8 @@ Table 5), numpy integer arithmetic plus hashlib's SHA-512:
 * public part: one byte per sample, image layout.  The report stores the
   inverse DCT of the remaining coefficients (private ones set to zero) as
   bytes.  Here that image is represented by P = (x - R) mod 256, where
-  R = rhe(sum_j q_j Bi[n_j][p] / 2^16), Bi = rhe(2^16 B), is the integer
-  inverse of the private integers: since x = IDCT(private part) +
+  R = floor((sum_j q_j Bi[n_j][p] + 2^15) / 2^16) (round half up),
+  Bi = rhe(2^16 B), is the integer inverse of the private integers: since x = IDCT(private part) +
   IDCT(rest) exactly, P differs from the inverse transform of the rest only by
   how far R is from IDCT(private part) (a bound is checked in the tests), and
   (R + P) mod 256 gives x back exactly.
@@ -75,7 +75,7 @@ def recon_private(q: np.ndarray, mask: int) -> np.ndarray:
     _, nat = private_positions(mask)
     Bi = inv_table()
     acc = np.asarray(q, np.int64) @ Bi[nat]       # (nb, 64), exact in int64
-    return rhe_shift(acc, INV_SHIFT)
+    return (acc + (1 << (INV_SHIFT - 1))) >> INV_SHIFT   # round half up
 
 
 def strong_keystream(q: np.ndarray) -> np.ndarray:

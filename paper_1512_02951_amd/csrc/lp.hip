@@ -316,14 +316,6 @@ __device__ __forceinline__ uint32_t rec_word(const f32x16 &y, int q4) {
   return w;
 }
 
-// Byte-wise a - b and a + b modulo 256 (no carry or borrow between bytes).
-__device__ __forceinline__ uint32_t bytes_sub(uint32_t a, uint32_t b) {
-  return ((a | 0x80808080u) - (b & 0x7f7f7f7fu)) ^ ((a ^ ~b) & 0x80808080u);
-}
-__device__ __forceinline__ uint32_t bytes_add(uint32_t a, uint32_t b) {
-  return ((a & 0x7f7f7f7fu) + (b & 0x7f7f7f7fu)) ^ ((a ^ b) & 0x80808080u);
-}
-
 // Inverse-transform operands of one half: lane half h holds coefficients
 // 16 s + 8 h + e (e = 0..7) of block jb; public ones are the stored 16-bit
 // values (pub16(slot) returns them), private ones the integers from LDS,

@@ -205,6 +205,14 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // truth table of a ^ b ^ c
 }
 
+// Byte-wise a - b and a + b modulo 256 (no carry or borrow between bytes).
+__device__ __forceinline__ uint32_t bytes_sub(uint32_t a, uint32_t b) {
+  return ((a | 0x80808080u) - (b & 0x7f7f7f7fu)) ^ ((a ^ ~b) & 0x80808080u);
+}
+__device__ __forceinline__ uint32_t bytes_add(uint32_t a, uint32_t b) {
+  return ((a & 0x7f7f7f7fu) + (b & 0x7f7f7f7fu)) ^ ((a ^ b) & 0x80808080u);
+}
+
 // One AES-128 encryption (FIPS-197 Sec. 5.1) of the state words s0..s3 with
 // the T-table formulation: each middle round is 16 table lookups whose byte
 // indices the compiler takes with sub-dword operand selection, and two

@@ -23,6 +23,7 @@ struct HostTables {
   uint8_t sbox[256];                     // FIPS-197 S-box
   uint32_t q2[64 * kQ2RowWords];         // integer basis limbs, see q2_acc()
   int32_t q2_int[64 * 64];               // round_half_even(2^20 B[n][p])
+  int32_t inv16[64 * 64];               // round_half_even(2^16 B[n][p]), pixel-domain inverse
   float cert_m[64];                      // max_p |B[n][p]| (rounded up), per natural index
   float cert_e[64];                      // 255 * sum_p |Bq/2^20 - B| (rounded up)
   DctK dct;                              // butterfly constants
@@ -105,6 +106,16 @@ int launch_dwt_frag(const DeviceState &ds, const Geom &g, const uint8_t *pix, in
                     const AesArgs &aes, hipStream_t stream);
 int launch_dwt_defrag(const DeviceState &ds, const Geom &g, const int16_t *pub, const uint8_t *priv,
                       const AesArgs &aes, uint8_t *pix, hipStream_t stream);
+
+// Pixel-domain formats: 11-bit private fields, byte public part, optional
+// SHA-512 strong level (pixel.hip).  At most kPixMaxPriv private coefficients.
+constexpr int kPixMaxPriv = 16;
+uint32_t pixel_tile_stride(uint32_t np);
+uint32_t pixel_last_tile_bytes(const Geom &g);
+int launch_pixel_frag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pix, uint8_t *pub,
+                      uint8_t *priv, const AesArgs &aes, hipStream_t stream);
+int launch_pixel_defrag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pub, const uint8_t *priv,
+                        const AesArgs &aes, uint8_t *pix, hipStream_t stream);
 
 // Differentiation form (softmask.hip).
 size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, uint32_t W);

@@ -6,6 +6,7 @@
 //    basis (report Sec. 6.4.2: separable 2-D DCT), in long double;
 //  * the integer basis round_half_even(2^20 B) of the private quantiser and
 //    its signed-byte limbs;
+//  * the integer basis round_half_even(2^16 B) of the pixel-domain inverse;
 //  * per-coefficient bounds used by the exactness certificate.
 #include <math.h>
 #include <string.h>
@@ -71,6 +72,7 @@ void build_dct(HostTables &t) {
           const long double scaled = ldexpl(bv, 20);
           const int32_t q = (int32_t)llrintl(scaled);  // default rounding: to nearest, ties to even
           qi[8 * y + x] = q;
+          t.inv16[n * 64 + 8 * y + x] = (int32_t)llrintl(ldexpl(bv, 16));
           rowsum += q;
           if (fabsl(bv) > maxabs) maxabs = fabsl(bv);
           errsum += fabsl((long double)q - scaled);

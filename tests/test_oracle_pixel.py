@@ -76,9 +76,9 @@ def test_dc_only_reconstruction_is_the_block_mean():
     R = px.recon_private(q, 1)
     blk = oracle.blocks_of(pix).astype(np.int64)
     s = blk.sum(1)
-    # q = rhe(S / 8), R = rhe(q / 8) at every sample
+    # q = rhe(S / 8), R = floor(q / 8 + 1/2) at every sample
     assert np.array_equal(q[:, 0], px.rhe_shift(s, 3))
-    assert np.array_equal(R, np.repeat(px.rhe_shift(q[:, 0], 3)[:, None], 64, 1))
+    assert np.array_equal(R, np.repeat(np.floor(q[:, 0] / 8 + 0.5).astype(np.int64)[:, None], 64, 1))
 
 
 @pytest.mark.parametrize("mask", [oracle.prefix_mask(2), oracle.prefix_mask(5), oracle.prefix_mask(9)])
