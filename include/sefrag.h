@@ -294,6 +294,54 @@ int pixel_defrag_image(const sf_desc *desc, int level, const uint8_t *d_public, 
                        const sf_aes_ctr *aes, uint8_t *d_pixels, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Security statistics (Sec. 6.6, Sec. 6.10, Eqs. (3)-(4), Table 14) of a
+ * protected byte image Y against its original X, both planar C x H x W
+ * (H, W positive multiples of 8; fewer than 2^32 samples), e.g. X the input
+ * and Y the public fragment of pixel_frag_image.  Written by the device into
+ * *d_out (device memory; copy it to the host after the stream has run):
+ *   hist_x, hist_y : byte histograms; chi2_y: sum (h - N/256)^2 / (N/256).
+ *   entropy_x/_y, joint_entropy : Eq. (3) in bits over the samples and the
+ *     pairs (x, y); mutual_information = H(X) + H(Y) - H(X,Y);
+ *     nmi = mutual_information / sqrt(H(X) H(Y)).
+ *   pair_x/_y[d] : exact moments (n, Sx, Sy, Sxx, Syy, Sxy) over every
+ *     adjacent pair of a plane, d = horizontal, vertical, diagonal (x the
+ *     upper / left sample), pooled over planes; corr_x/_y[d] their Pearson r
+ *     (the report samples 10,000 or 4,096 pairs; this is the population).
+ *   cross : (N, Sx, Sy, Sxx, Syy, Sxy) of X against Y; corr2 its Pearson r.
+ *   bits_differing, dif = 100 bits_differing / (8 N) (also the key
+ *     sensitivity measure of Sec. 6.10.6 when X, Y are two ciphertexts);
+ *     psnr = 10 log10(255^2 N / sum (x - y)^2) (inf when X = Y).
+ *   block_entropy_x/_y : mean, standard deviation, min, max over the 8x8
+ *     blocks of Eq. (3) over the block's 64 samples (h = 8, at most 6).
+ * d_block_entropy (optional, NULL to skip): 2 * C * (H/8) * (W/8) floats,
+ * the block entropies of X then of Y, block order of frag_image.
+ * d_ws: caller-owned device workspace of sf_stats_workspace_bytes() bytes,
+ * 16-byte aligned; its first 65536 uint32 hold the joint histogram
+ * (bin 256 x + y) after the call.  X and Y 16-byte aligned.  Errors:
+ * SF_EINVAL (NULL, misaligned, workspace too small), SF_ESHAPE, SF_EHIP.
+ * ------------------------------------------------------------------- */
+typedef struct sf_security_stats {
+  uint64_t samples;
+  uint64_t hist_x[256];
+  uint64_t hist_y[256];
+  uint64_t pair_x[3][6];
+  uint64_t pair_y[3][6];
+  uint64_t cross[6];
+  uint64_t bits_differing;
+  double chi2_y;
+  double entropy_x, entropy_y, joint_entropy, mutual_information, nmi;
+  double corr_x[3], corr_y[3];
+  double corr2, dif, psnr;
+  double block_entropy_x[4], block_entropy_y[4];
+} sf_security_stats;
+
+size_t sf_stats_workspace_bytes(void);
+
+int sf_security_stats_compute(const uint8_t *d_x, const uint8_t *d_y, uint32_t height, uint32_t width,
+                              uint32_t channels, void *d_ws, size_t ws_bytes, sf_security_stats *d_out,
+                              float *d_block_entropy, void *stream);
+
+/* ---------------------------------------------------------------------
  * Differentiation form: a soft per-frequency selection mask
  * m_n = sigmoid(l_n) over the 64 natural frequencies n = 8u + v, and the
  * public image it leaves, P = IDCT(DCT(x) * (1 - m)) per 8x8 block (the

@@ -385,6 +385,26 @@ int pixel_defrag_image(const sf_desc *desc, int level, const uint8_t *d_public, 
   return rc;
 }
 
+// ---- security statistics
+size_t sf_stats_workspace_bytes(void) { return stats_workspace_bytes(); }
+
+int sf_security_stats_compute(const uint8_t *d_x, const uint8_t *d_y, uint32_t H, uint32_t W, uint32_t C, void *d_ws,
+                              size_t ws_bytes, sf_security_stats *d_out, float *d_block_entropy, void *stream) {
+  if (!d_x || !d_y || !d_ws || !d_out) return fail(SF_EINVAL, "NULL buffer");
+  if (H == 0 || W == 0 || H % 8 || W % 8) return fail(SF_ESHAPE, "height and width must be positive multiples of 8");
+  if (C == 0) return fail(SF_ESHAPE, "channels must be >= 1");
+  if ((uint64_t)H * W * C >= (1ull << 32)) return fail(SF_ESHAPE, "image must hold fewer than 2^32 samples");
+  if (((uintptr_t)d_x | (uintptr_t)d_y | (uintptr_t)d_ws) & 15u) return fail(SF_EINVAL, "buffers must be 16-byte aligned");
+  if (((uintptr_t)d_out & 7u) || ((uintptr_t)d_block_entropy & 3u)) return fail(SF_EINVAL, "misaligned output");
+  if (ws_bytes < stats_workspace_bytes()) return fail(SF_EINVAL, "workspace too small");
+  DeviceState *ds;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  rc = launch_security_stats(d_x, d_y, H, W, C, d_ws, d_out, d_block_entropy, (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
 // ---- differentiation form
 static int sm_ptrs(const void *a, const void *b) {
   if (!a || !b) return fail(SF_EINVAL, "NULL buffer");

@@ -117,6 +117,11 @@ int launch_pixel_frag(const DeviceState &ds, const Geom &g, bool strong, const u
 int launch_pixel_defrag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pub, const uint8_t *priv,
                         const AesArgs &aes, uint8_t *pix, hipStream_t stream);
 
+// Security statistics (stats.hip).
+size_t stats_workspace_bytes();
+int launch_security_stats(const uint8_t *x, const uint8_t *y, uint32_t H, uint32_t W, uint32_t C, void *ws,
+                          sf_security_stats *out, float *block_entropy, hipStream_t stream);
+
 // Differentiation form (softmask.hip).
 size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, uint32_t W);
 int softmask_forward(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W, const float *logits,
