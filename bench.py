@@ -35,12 +35,12 @@ PROFILE = os.path.join(ROOT, "profiles", "frag_defrag_4096rgb_k5.md")
 
 
 def source_sha1():
-    """Hash of the kernel sources and the C ABI header."""
-    import glob
+    """Hash of the sources the headline frag / defrag kernels are compiled
+    from (their translation unit, its headers and the constant tables)."""
     import hashlib
     h = hashlib.sha1()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1512_02951_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "paper_1512_02951_amd", "csrc", "*.h")))
+    csrc = os.path.join(ROOT, "paper_1512_02951_amd", "csrc")
+    files = [os.path.join(csrc, n) for n in ("plain.hip", "plain_tile.h", "sf_device.h", "sf_internal.h", "tables.hip")]
     for f in files + [os.path.join(ROOT, "include", "sefrag.h")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -316,6 +316,20 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
             "ms_per_step": round(ms, 4), "MP/s": round(nsamp / 1e6 / (ms * 1e-3), 1),
             "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
         del pfr, py
+
+    # ---- security statistics of the strong-level public part against the image
+    from paper_1512_02951_amd import stats as sst
+    ys = pixel.pixel_frag_image(px_x[0], pk, True, wkey, wc[0]).public
+    runner = sst.StatsRunner(dev)
+    runner.launch(px_x[0], ys)
+    ms = time_graphs(torch, [_Eager(lambda: runner.launch(px_x[0], ys))], steps, warmup)
+    r = runner.result()
+    out["security_statistics"] = {
+        "workload": "4096^2 RGB image against its strong-level public part: histograms, chi-square, entropies, "
+                    "NMI (joint 256x256 histogram), block entropy, adjacent-pair correlations, corr2, Dif, PSNR",
+        "ms_per_call": round(ms, 4), "GB/s_inputs": round(2 * nsamp / (ms * 1e-3) / 1e9, 1),
+        "nmi": round(r["nmi"], 6), "corr_y_h": round(r["corr_y_h"], 6), "chi2_y": round(r["chi2_y"], 2),
+        "block_entropy_y_mean": round(r["block_entropy_y"][0], 5)}
     return out
 
 

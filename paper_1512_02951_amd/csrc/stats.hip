@@ -13,13 +13,14 @@
 //    multiply a zero; the directional sums of x and y are derived exactly from
 //    whole-plane sums minus the border sums the band kernel also gathers.
 //    Block entropy: per-wave LDS byte counters (256 per block, four to a
-//    word, ds_add), then each sample adds log2 of its value's count from an
-//    FP64 table; H = 6 - sum / 64.  Per-workgroup partial sums.
+//    word, ds_add), then the product of every sample's value count; H = 6 -
+//    log2(product) / 64.  Per-workgroup partial sums.
 //  * joint histogram: a workgroup owns the half of the 256 x 256 bins with
 //    x < 128 or x >= 128 as 32768 LDS counters (128 KB), counts a chunk of
 //    samples, then adds its non-zero bins to the global histogram.
-//  * finalize (one workgroup): reduces the partials in a fixed order, forms
-//    the histograms, entropies, NMI, chi-square and correlations in FP64.
+//  * rows (256 workgroups) and finalize (one workgroup): reduce the partials
+//    and the histogram in fixed orders, then form the histograms, entropies,
+//    NMI, chi-square and correlations in FP64.
 #include "sf_internal.h"
 
 namespace sf {
@@ -136,25 +137,32 @@ __device__ __forceinline__ void band_image_moments(const uint32_t (&w)[9], const
 }
 
 // Block entropy of the lane's half block (lanes 2k, 2k + 1 share block k of
-// the band): counts in LDS, then the sum of log2(count) over the samples.
-__device__ __forceinline__ double band_block_log_sum(const uint32_t (&w)[9], uint32_t *cnt, const double *log2tab,
-                                                     int lane) {
+// the band): counts in LDS, then the product of the counts of the lane's 32
+// samples' values.  sum_i log2(c_i) over the block is log2 of the two lanes'
+// products (each count <= 64, so the product is at most 2^384: no overflow in
+// FP64, relative error below 64 * 2^-53).
+__device__ __forceinline__ double band_block_count_product(const uint32_t (&w)[9], uint32_t *cnt, int lane) {
   uint32_t *blk = cnt + (lane >> 1) * 64;
-  // zero the block's 64 counter words (each lane of the pair 32)
-  uint4 *z = reinterpret_cast<uint4 *>(blk + 32 * (lane & 1));
+  // zero the wave's 32 x 64 counter words together: each store instruction
+  // covers 1 KB of consecutive words (per-block 16-byte stores at a 128-byte
+  // lane stride would all fall into the same few LDS banks)
+  uint4 *z = reinterpret_cast<uint4 *>(cnt);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) z[i] = make_uint4(0, 0, 0, 0);
+  for (int i = 0; i < 8; ++i) z[64 * i + lane] = make_uint4(0, 0, 0, 0);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // one row at a time (sched_barrier): all 32 accesses in flight at once
   // would hold twice the registers for no gain
+  // counter word of value v: (v / 4 + block) mod 64, so that lanes holding the
+  // same value (smooth regions) hit different LDS banks
+  const uint32_t rot = (uint32_t)(lane >> 1);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t v = (w[r] >> (8 * i)) & 0xffu;
-      atomicAdd(&blk[v >> 2], 1u << (8 * (v & 3u)));
+      atomicAdd(&blk[((v >> 2) + rot) & 63u], 1u << (8 * (v & 3u)));
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -162,17 +170,24 @@ __device__ __forceinline__ double band_block_log_sum(const uint32_t (&w)[9], uin
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const uint8_t *bytes = reinterpret_cast<const uint8_t *>(blk);
-  double s = 0.0;
+  // products of four counts are exact integers (<= 2^24): multiply those in
+  // 32-bit integers, then the eight partial products in FP64
+  double p = 1.0;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
+    uint32_t q = 1u;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s += log2tab[bytes[(w[r] >> (8 * i)) & 0xffu]];
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t v = (w[r] >> (8 * i)) & 0xffu;
+      q *= bytes[4u * (((v >> 2) + rot) & 63u) + (v & 3u)];
+    }
+    p *= (double)q;
     __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  return s;
+  return p;
 }
 
 struct BandArgs {
@@ -207,12 +222,9 @@ __device__ __forceinline__ void band_load(const uint8_t *img, const StatsGeom &g
 
 __global__ __launch_bounds__(kBandThreads) void stats_band_kernel(BandArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBandWaves][32 * 64];
-  __shared__ double s_log2[65];
   __shared__ Partial s_part[kBandWaves];
   const int lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (threadIdx.x < 65) s_log2[threadIdx.x] = threadIdx.x == 0 ? 0.0 : log2((double)threadIdx.x);
-  __syncthreads();
   const StatsGeom &g = a.g;
   uint32_t acc[kIntMoments];
 #pragma unroll
@@ -248,9 +260,9 @@ __global__ __launch_bounds__(kBandThreads) void stats_band_kernel(BandArgs a) {
         acc[kBitsDiff] += bits;
       }
       // block entropy (every lane takes part in the LDS steps)
-      double s = band_block_log_sum(w, s_cnt[wave], s_log2, lane);
-      s += __shfl_xor(s, 1, 64);
-      const double h = 6.0 - s * (1.0 / 64.0);
+      double pr = band_block_count_product(w, s_cnt[wave], lane);
+      pr *= __shfl_xor(pr, 1, 64);
+      const double h = 6.0 - log2(pr) * (1.0 / 64.0);
       if (valid && (lane & 1) == 0) {
         esum[im] += h;
         esq[im] += h * h;
@@ -345,11 +357,27 @@ __global__ __launch_bounds__(kJointThreads) void stats_joint_kernel(JointArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Reductions after the counting kernels, in the workspace (Reduced):
+//  * rows kernel, one workgroup per joint-histogram row j (x = j): the row
+//    sum (hist_x[j]), sum c log2 c over the row, and the column sums
+//    (hist_y) by 64-bit integer atomics; workgroups j < kIntMoments +
+//    kFltMoments also reduce one partial moment over the band workgroups.
+//  * finalize, one workgroup: everything else, from 256-entry arrays.
+// All floating sums use fixed trees, so the results do not depend on timing.
+struct Reduced {
+  uint64_t hx[256];
+  uint64_t hy[256];
+  double rowlog[256];
+  uint64_t m[kIntMoments];
+  double f[kFltMoments];
+};
+
 struct FinArgs {
   StatsGeom g;
   const Partial *partials;
   uint32_t nparts;
   const uint32_t *hist;
+  Reduced *red;
   sf_security_stats *out;
 };
 
@@ -366,20 +394,59 @@ __device__ double pearson(uint64_t n, uint64_t sx, uint64_t sy, uint64_t sxx, ui
   return (double)num / sqrt((double)dx * (double)dy);
 }
 
-__device__ double block_sum(double v, double *sh) {
+template <class T, class Op>
+__device__ T block_reduce(T v, T *sh, Op op) {
   const int t = threadIdx.x;
   sh[t] = v;
   __syncthreads();
   for (int s = kFinThreads / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
+    if (t < s) sh[t] = op(sh[t], sh[t + s]);
     __syncthreads();
   }
-  const double r = sh[0];
+  const T r = sh[0];
   __syncthreads();
   return r;
 }
 
+__device__ double block_sum(double v, double *sh) {
+  return block_reduce(v, sh, [](double a, double b) { return a + b; });
+}
+
 __device__ double clog2c(uint64_t c) { return c ? (double)c * log2((double)c) : 0.0; }
+
+__global__ __launch_bounds__(kFinThreads) void stats_rows_kernel(FinArgs a) {
+  __shared__ double s_d[kFinThreads];
+  __shared__ uint64_t s_u[kFinThreads];
+  const int t = threadIdx.x;
+  const uint32_t j = blockIdx.x;
+  const uint32_t c = a.hist[j * 256u + t];
+  atomicAdd(reinterpret_cast<unsigned long long *>(&a.red->hy[t]), (unsigned long long)c);
+  const uint64_t rs = block_reduce<uint64_t>(c, s_u, [](uint64_t x, uint64_t y) { return x + y; });
+  const double rl = block_sum(clog2c(c), s_d);
+  if (t == 0) {
+    a.red->hx[j] = rs;
+    a.red->rowlog[j] = rl;
+  }
+  // one partial moment per workgroup: a fixed split over the threads, then a tree
+  if (j < (uint32_t)kIntMoments) {
+    uint64_t v = 0;
+    for (uint32_t p = t; p < a.nparts; p += kFinThreads) v += a.partials[p].m[j];
+    v = block_reduce<uint64_t>(v, s_u, [](uint64_t x, uint64_t y) { return x + y; });
+    if (t == 0) a.red->m[j] = v;
+  } else if (j < (uint32_t)(kIntMoments + kFltMoments)) {
+    const int i = (int)j - kIntMoments;
+    const int kind = i & 3;  // 0, 1: sums; 2: min; 3: max
+    double v = kind == 2 ? 1e300 : kind == 3 ? -1e300 : 0.0;
+    for (uint32_t p = t; p < a.nparts; p += kFinThreads) {
+      const double w = a.partials[p].f[i];
+      v = kind == 2 ? fmin(v, w) : kind == 3 ? fmax(v, w) : v + w;
+    }
+    v = block_reduce<double>(v, s_d, [kind](double x, double y) {
+      return kind == 2 ? fmin(x, y) : kind == 3 ? fmax(x, y) : x + y;
+    });
+    if (t == 0) a.red->f[i] = v;
+  }
+}
 
 __global__ __launch_bounds__(kFinThreads) void stats_finalize_kernel(FinArgs a) {
   __shared__ uint64_t s_m[kIntMoments];
@@ -388,29 +455,13 @@ __global__ __launch_bounds__(kFinThreads) void stats_finalize_kernel(FinArgs a) 
   const int t = threadIdx.x;
   const StatsGeom &g = a.g;
   sf_security_stats *o = a.out;
-  if (t < kIntMoments) {
-    uint64_t v = 0;
-    for (uint32_t p = 0; p < a.nparts; ++p) v += a.partials[p].m[t];
-    s_m[t] = v;
-  } else if (t >= 64 && t < 64 + kFltMoments) {
-    const int i = t - 64;
-    double v = a.partials[0].f[i];
-    for (uint32_t p = 1; p < a.nparts; ++p) {
-      const double w = a.partials[p].f[i];
-      v = (i & 3) == 2 ? fmin(v, w) : (i & 3) == 3 ? fmax(v, w) : v + w;
-    }
-    s_f[i] = v;
-  }
-  // marginal histograms (thread t: value t)
-  uint64_t hx = 0, hy = 0;
-  for (int j = 0; j < 256; ++j) {
-    hx += a.hist[t * 256 + j];
-    hy += a.hist[j * 256 + t];
-  }
+  const Reduced *rd = a.red;
+  if (t < kIntMoments) s_m[t] = rd->m[t];
+  else if (t >= 64 && t < 64 + kFltMoments) s_f[t - 64] = rd->f[t - 64];
+  const uint64_t hx = rd->hx[t], hy = rd->hy[t];
   o->hist_x[t] = hx;
   o->hist_y[t] = hy;
-  double jl = 0.0;
-  for (int j = 0; j < 256; ++j) jl += clog2c(a.hist[t * 256 + j]);
+  const double jl = rd->rowlog[t];
   __syncthreads();
   const uint64_t N = (uint64_t)g.C * g.H * g.W;
   const double dN = (double)N;
@@ -491,14 +542,23 @@ StatsGeom stats_geom(uint32_t H, uint32_t W, uint32_t C) {
 
 }  // namespace
 
-size_t stats_workspace_bytes() { return 65536 * sizeof(uint32_t) + kBandGrid * sizeof(Partial); }
+constexpr size_t kHistBytes = 65536 * sizeof(uint32_t);
+constexpr size_t kPartBytes = kBandGrid * sizeof(Partial);
+static_assert(kHistBytes % 16 == 0 && kPartBytes % 16 == 0, "workspace parts stay 16-byte aligned");
+
+size_t stats_workspace_bytes() { return kHistBytes + kPartBytes + sizeof(Reduced); }
 
 int launch_security_stats(const uint8_t *x, const uint8_t *y, uint32_t H, uint32_t W, uint32_t C, void *ws,
                           sf_security_stats *out, float *block_entropy, hipStream_t stream) {
   const StatsGeom g = stats_geom(H, W, C);
   uint32_t *hist = static_cast<uint32_t *>(ws);
-  Partial *parts = reinterpret_cast<Partial *>(static_cast<uint8_t *>(ws) + 65536 * sizeof(uint32_t));
+  Partial *parts = reinterpret_cast<Partial *>(static_cast<uint8_t *>(ws) + kHistBytes);
+  Reduced *red = reinterpret_cast<Reduced *>(static_cast<uint8_t *>(ws) + kHistBytes + kPartBytes);
+  // the histogram and the column sums start at zero (a fill kernel, not a
+  // memset, so the sequence can be captured in a graph)
   hipLaunchKernelGGL(stats_clear_kernel, dim3(64), dim3(256), 0, stream, hist, 65536u);
+  hipLaunchKernelGGL(stats_clear_kernel, dim3(1), dim3(256), 0, stream, reinterpret_cast<uint32_t *>(red->hy),
+                     (uint32_t)(sizeof(red->hy) / 4));
   BandArgs b{g, x, y, parts, block_entropy};
   const uint32_t need = (g.nbands + kBandWaves - 1) / kBandWaves;
   const uint32_t grid = need < (uint32_t)kBandGrid ? need : (uint32_t)kBandGrid;
@@ -512,7 +572,8 @@ int launch_security_stats(const uint8_t *x, const uint8_t *y, uint32_t H, uint32
   j.per_chunk = (j.nvec + chunks - 1) / chunks;
   j.hist = hist;
   hipLaunchKernelGGL(stats_joint_kernel, dim3((uint32_t)chunks, 2), dim3(kJointThreads), 0, stream, j);
-  FinArgs f{g, parts, grid, hist, out};
+  FinArgs f{g, parts, grid, hist, red, out};
+  hipLaunchKernelGGL(stats_rows_kernel, dim3(256), dim3(kFinThreads), 0, stream, f);
   hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kFinThreads), 0, stream, f);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "security statistics launch");
