@@ -172,20 +172,40 @@ def _bytes_plain(H, W, C, npriv, pub_elt=4, residual=False):
     return algorithmic_bytes(H, W, C, npriv, pub_elt) + (H * W * C if residual else 0)
 
 
-def measure_forms(sf, torch, synth, dev, steps, warmup):
+FORMS = ("precision", "batching", "differentiation", "wavelet", "pixel", "statistics")
+
+
+def measure_forms(sf, torch, synth, dev, steps, warmup, which=None):
     """Companion figures for the other forms, each on its own workload (these
     are not the headline number): the precision form (16 images 8192^2 gray,
     DC + 9 AC private) as FP32 vs fp16 vs bf16 round trips; the batching form
     (2000 mixed images) with the tuner's schedule; the differentiation form
     (64 x 1024^2 FP32): statistics pass, forward with P, adjoint backward and
-    the 200-step tuning loop; the wavelet form on the 4096^2 RGB image.  Figures are averages over direct launches; the
-    batching form is also timed as a HIP-graph replay, its intended use."""
-    from paper_1512_02951_amd import softmask as sm
-    from paper_1512_02951_amd.batch import Batch
+    the 200-step tuning loop; the wavelet form, the pixel-domain formats (both
+    levels) and the security statistics on the 4096^2 RGB image.  which: the
+    subset of FORMS to run (all by default).  Figures are averages over direct
+    launches; the batching form is also timed as a HIP-graph replay, its
+    intended use."""
+    which = set(FORMS if which is None else which)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     out = {}
+    if "precision" in which:
+        _form_precision(sf, torch, synth, dev, steps, warmup, status, out)
+    if "batching" in which:
+        _form_batching(sf, torch, synth, dev, steps, warmup, status, out)
+    if "differentiation" in which:
+        _form_differentiation(sf, torch, synth, dev, steps, warmup, out)
+    S, C = 4096, 3
+    wkey = synth.aes_key(2)
+    wc = [synth.ctr0(2, i) for i in range(2)]
+    if "wavelet" in which:
+        _form_wavelet(torch, synth, dev, steps, warmup, S, C, wkey, wc, out)
+    if "pixel" in which or "statistics" in which:
+        _form_pixel_stats(sf, torch, synth, dev, steps, warmup, S, C, wkey, wc, which, out)
+    return out
 
-    # ---- precision form
+
+def _form_precision(sf, torch, synth, dev, steps, warmup, status, out):
     n_img, S, k = 16, 8192, 9
     mask, key = sf.prefix_mask(k), synth.aes_key(3)
     xs = [synth.image(S, S, 1, 3, i, device=dev) for i in range(n_img)]
@@ -213,7 +233,9 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
                         **prec_res}
     del xs
 
-    # ---- batching form
+
+def _form_batching(sf, torch, synth, dev, steps, warmup, status, out):
+    from paper_1512_02951_amd.batch import Batch
     specs = synth.batch_specs()
     bkey = synth.aes_key(4)
     imgs = [synth.image(h, w, c, 4, i, device=dev) for i, (h, w, c, kk) in enumerate(specs)]
@@ -238,7 +260,9 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
                        "direct_launch_ms_per_step": round(ms_direct, 4)}
     del imgs, b, gb
 
-    # ---- differentiation form
+
+def _form_differentiation(sf, torch, synth, dev, steps, warmup, out):
+    from paper_1512_02951_amd import softmask as sm
     B, Hs, Ws = 64, 1024, 1024
     x = synth.softmask_images(B, Hs, Ws, device=dev)
     l = torch.from_numpy(synth.logits_init().astype("float32")).to(dev)
@@ -264,14 +288,13 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
     gt = _Eager(lambda: sf.check(L.sf_softmask_tune(*tune_args, sf._stream(None))))
     res["tune_200_adam_steps"] = {"ms": round(time_graphs(torch, [gt], 5, 1), 4)}
     out["differentiation"] = {"workload": "64 x 1024^2 FP32 in [0, 1], soft mask over 64 frequencies", **res}
-    del x, G, stats
 
-    # ---- wavelet form (LeGall 5/3, two levels per 8x8 block, 2x2 LL2 private)
+
+def _form_wavelet(torch, synth, dev, steps, warmup, S, C, wkey, wc, out):
+    """LeGall 5/3, two levels per 8x8 block, 2x2 LL2 private."""
     from paper_1512_02951_amd import dwt
-    S, C = 4096, 3
-    wkey = synth.aes_key(2)
+    nsamp = C * S * S
     wx = [synth.image(S, S, C, 2, i, device=dev) for i in range(2)]
-    wc = [synth.ctr0(2, i) for i in range(2)]
     wfr = [dwt.dwt_frag_image(x, wkey, c) for x, c in zip(wx, wc)]
     wy = [torch.empty_like(x) for x in wx]
     it = [0]
@@ -283,19 +306,21 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
         dwt.dwt_defrag_image(wfr[i], wkey, wc[i], out=wy[i])
     ms = time_graphs(torch, [_Eager(wrt)], steps, warmup)
     assert all(torch.equal(x, y) for x, y in zip(wx, wy))
-    nsamp = C * S * S
     # frag: 1 B in, 2 B out per sample; defrag: 2 B in, 1 B out
     out["wavelet"] = {"workload": "4096^2 RGB uint8, LeGall 5/3 two levels per 8x8 block, LL2 (4 of 64) private, "
                                   "round trip (exact)",
                       "ms_per_step": round(ms, 4), "MP/s": round(nsamp / 1e6 / (ms * 1e-3), 1),
                       "GB/s": round(6 * nsamp / (ms * 1e-3) / 1e9, 1)}
-    del wx, wy, wfr
 
-    # ---- pixel-domain formats (11-bit private fields, byte public), both levels
+
+def _form_pixel_stats(sf, torch, synth, dev, steps, warmup, S, C, wkey, wc, which, out):
+    """Pixel-domain formats (11-bit private fields, byte public), both levels,
+    and the security statistics of the strong-level public part."""
     from paper_1512_02951_amd import pixel
+    nsamp = C * S * S
     pk = sf.prefix_mask(5)
     px_x = [synth.image(S, S, C, 2, i, device=dev) for i in range(2)]
-    for strong in (False, True):
+    for strong in ((False, True) if "pixel" in which else ()):
         pfr = [pixel.pixel_frag_image(x, pk, strong, wkey, c) for x, c in zip(px_x, wc)]
         py = [torch.empty_like(x) for x in px_x]
         pit = [0]
@@ -316,8 +341,8 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
             "ms_per_step": round(ms, 4), "MP/s": round(nsamp / 1e6 / (ms * 1e-3), 1),
             "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
         del pfr, py
-
-    # ---- security statistics of the strong-level public part against the image
+    if "statistics" not in which:
+        return
     from paper_1512_02951_amd import stats as sst
     ys = pixel.pixel_frag_image(px_x[0], pk, True, wkey, wc[0]).public
     runner = sst.StatsRunner(dev)
@@ -330,7 +355,6 @@ def measure_forms(sf, torch, synth, dev, steps, warmup):
         "ms_per_call": round(ms, 4), "GB/s_inputs": round(2 * nsamp / (ms * 1e-3) / 1e9, 1),
         "nmi": round(r["nmi"], 6), "corr_y_h": round(r["corr_y_h"], 6), "chi2_y": round(r["chi2_y"], 2),
         "block_entropy_y_mean": round(r["block_entropy_y"][0], 5)}
-    return out
 
 
 def main():
@@ -341,7 +365,9 @@ def main():
     ap.add_argument("--sets", type=int, default=4, help="disjoint buffer sets rotated across steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--no-forms", action="store_true", help="skip the companion figures of the three forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the companion figures of the other forms")
+    ap.add_argument("--forms", default=",".join(FORMS),
+                    help="comma-separated subset of the companion figures: " + ",".join(FORMS))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference kernel for HBM byte counters)")
     ap.add_argument("--graph", action="store_true", help="replay one HIP graph per step instead of direct launches")
@@ -413,7 +439,8 @@ def main():
     if not args.no_forms:
         del sets
         torch.cuda.empty_cache()
-        out["forms"] = measure_forms(sf, torch, synth, dev, max(args.steps // 10, 5), 2)
+        out["forms"] = measure_forms(sf, torch, synth, dev, max(args.steps // 10, 5), 2,
+                                     [f for f in args.forms.split(",") if f])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)
