@@ -29,6 +29,7 @@ namespace {
 constexpr int kBandWaves = 4;
 constexpr int kBandThreads = 64 * kBandWaves;
 constexpr int kBandGrid = 1024;  // fixed: the partial slots are per workgroup
+constexpr uint32_t kFlushBands = 256;
 constexpr int kJointThreads = 1024;
 constexpr uint32_t kHalfBins = 32768;
 constexpr int kFinThreads = 256;
@@ -74,10 +75,10 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// One image's moments over one band; adds into acc.  32-bit lane sums hold:
-// a band adds at most 32 * 255^2 per lane, and with the grid fixed at
-// kBandGrid workgroups a wave takes at most 512 bands of an image of fewer
-// than 2^32 samples (2^32 / 2048 bands / 4096 waves), 1.07e9 < 2^32.
+// One image's moments over one band; adds into acc.  A band adds at most
+// 32 * 255^2 = 2 080 800 to a lane's 32-bit sum; the kernel moves the lane
+// sums into the wave's 64-bit record every kFlushBands bands (256 * 2 080 800
+// < 2^32), so no image shape can wrap them.
 __device__ __forceinline__ void band_image_moments(const uint32_t (&w)[9], const uint32_t (&nx)[9], bool top,
                                                    bool bottom, bool left, bool right, uint32_t *acc) {
   uint32_t t1 = 0, t2 = 0, sh = 0, sv = 0, sd = 0;
@@ -229,10 +230,29 @@ __global__ __launch_bounds__(kBandThreads) void stats_band_kernel(BandArgs a) {
   uint32_t acc[kIntMoments];
 #pragma unroll
   for (int i = 0; i < kIntMoments; ++i) acc[i] = 0;
+  if (lane == 0)
+    for (int i = 0; i < kIntMoments; ++i) s_part[wave].m[i] = 0;
+  // lane sums into the wave's 64-bit record, one sum at a time: interleaving
+  // all of them holds every partial in registers at once, which is what would
+  // set this kernel's register count
+  auto flush = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < kIntMoments; ++i) {
+      const uint64_t v = wave_sum((uint64_t)acc[i]);
+      if (lane == 0) s_part[wave].m[i] += v;
+      acc[i] = 0;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
   double esum[2] = {0.0, 0.0}, esq[2] = {0.0, 0.0};
   double emin[2] = {1e300, 1e300}, emax[2] = {-1e300, -1e300};
   const uint64_t nb = (uint64_t)g.C * g.By * g.Bx;
+  uint32_t since_flush = 0;
   for (uint32_t band = blockIdx.x * kBandWaves + wave; band < g.nbands; band += gridDim.x * kBandWaves) {
+    if (++since_flush > kFlushBands) {
+      flush();
+      since_flush = 1;
+    }
     const uint32_t bx = band % g.nbx, rest = band / g.nbx;
     const uint32_t by = rest % g.By, plane = rest / g.By;
     const uint32_t wc = bx * 64u + (uint32_t)lane;
@@ -273,14 +293,7 @@ __global__ __launch_bounds__(kBandThreads) void stats_band_kernel(BandArgs a) {
     }
   }
   // wave, then workgroup reduction into this workgroup's partial slot
-  // one sum at a time: interleaving all of them holds every partial in
-  // registers at once, which is what sets this kernel's register count
-#pragma unroll
-  for (int i = 0; i < kIntMoments; ++i) {
-    const uint64_t v = wave_sum((uint64_t)acc[i]);
-    if (lane == 0) s_part[wave].m[i] = v;
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  flush();
   double fl[kFltMoments];
 #pragma unroll
   for (int im = 0; im < 2; ++im) {

@@ -112,6 +112,28 @@ def test_full_size_4096_rgb_strong_public():
     assert abs(got["block_entropy_y"][0] - ost.expected_block_entropy_uniform()) < 0.01
 
 
+def test_tall_narrow_image_sums_stay_exact():
+    # W = 8: one lane pair per band, 2^24 bands (4096 per wave): far more than
+    # a 32-bit lane sum of squares could hold without the periodic flush.
+    # Constant images give every moment in closed form.
+    C, H, W = 1, 1 << 27, 8
+    x = torch.full((C, H, W), 255, dtype=torch.uint8, device="cuda")
+    y = torch.full((C, H, W), 254, dtype=torch.uint8, device="cuda")
+    r = stats.StatsRunner(x.device)
+    r.launch(x, y)
+    g = r.result()
+    N = C * H * W
+    n = {"h": H * (W - 1), "v": (H - 1) * W, "d": (H - 1) * (W - 1)}
+    for d in ost.DIRS:
+        assert g["moments_x_" + d] == (n[d], 255 * n[d], 255 * n[d], 65025 * n[d], 65025 * n[d], 65025 * n[d])
+        assert g["moments_y_" + d] == (n[d], 254 * n[d], 254 * n[d], 64516 * n[d], 64516 * n[d], 64516 * n[d])
+    assert g["cross"] == (N, 255 * N, 254 * N, 65025 * N, 64516 * N, 255 * 254 * N)
+    assert g["bits_differing"] == N                      # 255 ^ 254 = 1: one bit per sample
+    assert g["hist_x"][255] == N and g["hist_y"][254] == N
+    assert max(abs(v) for v in g["block_entropy_x"]) < 1e-12
+    assert abs(g["psnr"] - 10 * math.log10(255 ** 2)) < 1e-12
+
+
 def test_errors():
     x = torch.zeros((1, 12, 16), dtype=torch.uint8, device="cuda")
     with pytest.raises(sf.SefragError) as e:
