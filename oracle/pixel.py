@@ -24,8 +24,15 @@ Table 5), numpy integer arithmetic plus hashlib's SHA-512:
   how far R is from IDCT(private part) (a bound is checked in the tests), and
   (R + P) mod 256 gives x back exactly.
 * strong level (Sec. 6.3.2, Fig. 8): the 64 public bytes of a block are
-  XORed with the SHA-512 digest (FIPS 180-4) of the block's private integers,
-  int16 little-endian in zigzag order; digest byte p masks sample p = 8y + x.
+  XORed with the SHA-512 digest (FIPS 180-4) of the block's private integers
+  as stored, int16 little-endian in zigzag order; digest byte p masks sample
+  p = 8y + x.
+* 8-bit storage (Sec. 6.4.3, Table 5, lossy): AC fields of a sign bit above a
+  7-bit magnitude, clamped to 127; DC keeps 11 bits.  The public part is made
+  from the exact integers (as the report's public image does not depend on how
+  the private part is stored), so defragmentation restores x exactly wherever
+  no private AC was clamped and loses only what the clamping removed.
+  ``ac_bits`` = 10 (11-bit fields, the default) or 7 (8-bit fields).
 """
 from __future__ import annotations
 
@@ -89,72 +96,102 @@ def strong_keystream(q: np.ndarray) -> np.ndarray:
     return out
 
 
-def _fields(q: np.ndarray, mask: int) -> np.ndarray:
+def field_widths(mask: int, ac_bits: int = 10):
+    """Bits of each private field in zigzag order: 11 for DC, ac_bits + 1 for AC."""
     zpos, _ = private_positions(mask)
-    q = np.asarray(q, np.int64)
+    return [FIELD_BITS if z == 0 else ac_bits + 1 for z in zpos]
+
+
+def record_bits(mask: int, ac_bits: int = 10) -> int:
+    return sum(field_widths(mask, ac_bits))
+
+
+def stored_ints(q: np.ndarray, mask: int, ac_bits: int = 10) -> np.ndarray:
+    """The private integers as the fields hold them: AC magnitudes clamped to
+    2^ac_bits - 1 (no clamping ever happens at 10 bits: |AC| <= 1020)."""
+    zpos, _ = private_positions(mask)
+    q = np.array(q, np.int64)
+    lim = (1 << ac_bits) - 1
+    for j, z in enumerate(zpos):
+        if z != 0:
+            q[:, j] = np.clip(q[:, j], -lim, lim)
+    return q
+
+
+def _fields(q: np.ndarray, mask: int, ac_bits: int = 10) -> np.ndarray:
+    zpos, _ = private_positions(mask)
+    q = stored_ints(q, mask, ac_bits)
     f = np.empty(q.shape, np.int64)
     for j, z in enumerate(zpos):
         if z == 0:
             assert q[:, j].min(initial=0) >= 0 and q[:, j].max(initial=0) < 2 ** FIELD_BITS
             f[:, j] = q[:, j]
         else:
-            mag = np.abs(q[:, j])
-            assert mag.max(initial=0) < 2 ** (FIELD_BITS - 1)
-            f[:, j] = mag | ((q[:, j] < 0).astype(np.int64) << (FIELD_BITS - 1))
+            f[:, j] = np.abs(q[:, j]) | ((q[:, j] < 0).astype(np.int64) << ac_bits)
     return f
 
 
-def _unfields(f: np.ndarray, mask: int) -> np.ndarray:
+def _unfields(f: np.ndarray, mask: int, ac_bits: int = 10) -> np.ndarray:
     zpos, _ = private_positions(mask)
     q = np.empty(f.shape, np.int64)
     for j, z in enumerate(zpos):
         if z == 0:
             q[:, j] = f[:, j]
         else:
-            mag = f[:, j] & ((1 << (FIELD_BITS - 1)) - 1)
-            q[:, j] = np.where((f[:, j] >> (FIELD_BITS - 1)) & 1, -mag, mag)
+            mag = f[:, j] & ((1 << ac_bits) - 1)
+            q[:, j] = np.where((f[:, j] >> ac_bits) & 1, -mag, mag)
     return q
 
 
-def tile_stride(P: int) -> int:
-    return 16 * ((88 * P + 15) // 16)
+def tile_stride(P: int, rec_bits: int | None = None) -> int:
+    """Bytes per full tile: 64 records of rec_bits (11 P by default), rounded up to 16."""
+    rb = FIELD_BITS * P if rec_bits is None else rec_bits
+    return 16 * ((8 * rb + 15) // 16)
 
 
-def private_bytes(nb: int, P: int) -> int:
+def private_bytes(nb: int, P: int, rec_bits: int | None = None) -> int:
     if nb == 0:
         return 0
+    rb = FIELD_BITS * P if rec_bits is None else rec_bits
     nt_last = nb - 64 * ((nb - 1) // 64)
-    return ((nb - 1) // 64) * tile_stride(P) + (FIELD_BITS * P * nt_last + 7) // 8
+    return ((nb - 1) // 64) * tile_stride(P, rb) + (rb * nt_last + 7) // 8
 
 
-def pack11(q: np.ndarray, mask: int) -> np.ndarray:
-    """(nb, P) private integers -> packed private bytes (tile streams)."""
-    f = _fields(q, mask)
+def pack11(q: np.ndarray, mask: int, ac_bits: int = 10) -> np.ndarray:
+    """(nb, P) private integers -> packed private bytes (tile streams); the
+    fields of a record follow each other, a tile's records likewise."""
+    f = _fields(q, mask, ac_bits)
+    widths = field_widths(mask, ac_bits)
     nb, P = f.shape
-    out = np.zeros(private_bytes(nb, P), np.uint8)
-    st = tile_stride(P)
+    rb = sum(widths)
+    out = np.zeros(private_bytes(nb, P, rb), np.uint8)
+    st = tile_stride(P, rb)
     for t0 in range(0, nb, 64):
         ft = f[t0:t0 + 64]
-        bits = ((ft[..., None] >> np.arange(FIELD_BITS)) & 1).astype(np.uint8).reshape(-1)
-        by = np.packbits(bits, bitorder="little")
+        bits = np.concatenate([((ft[:, j:j + 1] >> np.arange(w)) & 1) for j, w in enumerate(widths)], axis=1)
+        by = np.packbits(bits.astype(np.uint8).reshape(-1), bitorder="little")
         base = (t0 // 64) * st
         out[base:base + by.size] = by
     return out
 
 
-def unpack11(data: np.ndarray, nb: int, mask: int) -> np.ndarray:
-    """Inverse of pack11."""
+def unpack11(data: np.ndarray, nb: int, mask: int, ac_bits: int = 10) -> np.ndarray:
+    """Inverse of pack11 (returns the stored integers)."""
     P = popcount(mask)
+    widths = field_widths(mask, ac_bits)
+    rb = sum(widths)
     data = np.asarray(data, np.uint8)
-    st = tile_stride(P)
+    st = tile_stride(P, rb)
     f = np.zeros((nb, P), np.int64)
+    offs = np.concatenate([[0], np.cumsum(widths)])
     for t0 in range(0, nb, 64):
         nt = min(64, nb - t0)
-        nbits = FIELD_BITS * P * nt
+        nbits = rb * nt
         base = (t0 // 64) * st
-        bits = np.unpackbits(data[base:base + (nbits + 7) // 8], bitorder="little")[:nbits]
-        f[t0:t0 + nt] = (bits.reshape(nt, P, FIELD_BITS).astype(np.int64) << np.arange(FIELD_BITS)).sum(-1)
-    return _unfields(f, mask)
+        bits = np.unpackbits(data[base:base + (nbits + 7) // 8], bitorder="little")[:nbits].reshape(nt, rb)
+        for j, w in enumerate(widths):
+            f[t0:t0 + nt, j] = (bits[:, offs[j]:offs[j] + w].astype(np.int64) << np.arange(w)).sum(-1)
+    return _unfields(f, mask, ac_bits)
 
 
 def _unblocks(v: np.ndarray, shape) -> np.ndarray:
@@ -162,17 +199,19 @@ def _unblocks(v: np.ndarray, shape) -> np.ndarray:
     return v.reshape(C, H // 8, W // 8, 8, 8).transpose(0, 1, 3, 2, 4).reshape(C, H, W)
 
 
-def frag(pix: np.ndarray, mask: int, strong: bool = False, key: bytes | None = None, ctr0: bytes | None = None):
+def frag(pix: np.ndarray, mask: int, strong: bool = False, key: bytes | None = None, ctr0: bytes | None = None,
+         ac_bits: int = 10):
     """Returns dict: public (C, H, W) uint8, private (packed plain bytes),
-    cipher (bytes or None), q (nb, P) private integers."""
+    cipher (bytes or None), q (nb, P) private integers (exact, before any
+    clamping of the stored fields)."""
     pix = _planes(pix)
     blk = blocks_of(pix).astype(np.int64)
     q = private_ints(pix, mask)
     R = recon_private(q, mask)
     pub = ((blk - R) & 0xFF).astype(np.uint8)
     if strong:
-        pub ^= strong_keystream(q)
-    plain = pack11(q, mask)
+        pub ^= strong_keystream(stored_ints(q, mask, ac_bits))
+    plain = pack11(q, mask, ac_bits)
     out = {"public": _unblocks(pub, pix.shape), "private": plain, "cipher": None, "q": q}
     if key is not None:
         out["cipher"] = ctr_xor(key, ctr0 if ctr0 is not None else bytes(16), plain)
@@ -180,12 +219,13 @@ def frag(pix: np.ndarray, mask: int, strong: bool = False, key: bytes | None = N
 
 
 def defrag(shape, mask: int, public: np.ndarray, private: np.ndarray | None = None, strong: bool = False,
-           key: bytes | None = None, ctr0: bytes | None = None, cipher: np.ndarray | None = None) -> np.ndarray:
+           key: bytes | None = None, ctr0: bytes | None = None, cipher: np.ndarray | None = None,
+           ac_bits: int = 10) -> np.ndarray:
     C, H, W = shape
     nb = C * (H // 8) * (W // 8)
     if cipher is not None:
         private = ctr_xor(key, ctr0 if ctr0 is not None else bytes(16), np.asarray(cipher, np.uint8))
-    q = unpack11(private, nb, mask)
+    q = unpack11(private, nb, mask, ac_bits)
     pub = blocks_of(np.asarray(public, np.uint8).reshape(C, H, W)).copy()
     if strong:
         pub ^= strong_keystream(q)
@@ -193,11 +233,12 @@ def defrag(shape, mask: int, public: np.ndarray, private: np.ndarray | None = No
     return _unblocks(x.astype(np.uint8), shape)
 
 
-def fragment_bytes(C: int, H: int, W: int, mask: int):
+def fragment_bytes(C: int, H: int, W: int, mask: int, ac_bits: int = 10):
     """(public_bytes, private_bytes)."""
     nb = C * (H // 8) * (W // 8)
-    return C * H * W, private_bytes(nb, popcount(mask))
+    return C * H * W, private_bytes(nb, popcount(mask), record_bits(mask, ac_bits))
 
 
 __all__ = ["inv_table", "rhe_shift", "private_positions", "private_ints", "recon_private", "strong_keystream",
-           "tile_stride", "private_bytes", "pack11", "unpack11", "frag", "defrag", "fragment_bytes"]
+           "field_widths", "record_bits", "stored_ints", "tile_stride", "private_bytes", "pack11", "unpack11", "frag",
+           "defrag", "fragment_bytes"]

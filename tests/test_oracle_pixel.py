@@ -154,3 +154,48 @@ def test_strong_level_statistics_of_the_report():
     r_strong = np.corrcoef(strong[:, :-1].ravel(), strong[:, 1:].ravel())[0, 1]
     r_orig = np.corrcoef(pix[0][:, :-1].ravel().astype(float), pix[0][:, 1:].ravel().astype(float))[0, 1]
     assert abs(r_strong) < 0.01 and r_orig > 0.5
+
+
+def test_8bit_storage_fraction_matches_the_report():
+    # Sec. 6.4.3: DC in 11 bits and 5 AC in 8 bits = 5/64 + 11/8/64 = 9.96 % of the image
+    mask = oracle.prefix_mask(5)
+    assert px.record_bits(mask, 7) == 11 + 5 * 8
+    assert round(100 * px.record_bits(mask, 7) / 512, 2) == 9.96
+    # tiles start on AES-block boundaries: 64 records of 51 bits are 408 bytes,
+    # padded to 416 (the stored fragment is 10.16 % of the image)
+    assert px.tile_stride(6, 51) == 416
+    _, priv = px.fragment_bytes(1, 4096, 4096, mask, ac_bits=7)
+    assert priv == 4095 * 416 + 408  # the last tile is not padded
+
+
+def test_8bit_fields_hand_example_and_clamping():
+    # DC 2040 in 11 bits; AC -200 clamps to -127: sign bit 7 above magnitude 127
+    q = np.array([[2040, -200]])
+    v = 0x7F8 | ((0x80 | 127) << 11)
+    assert px.pack11(q, 0b11, ac_bits=7).tolist() == [v & 0xFF, (v >> 8) & 0xFF, (v >> 16) & 0xFF]
+    assert px.unpack11(px.pack11(q, 0b11, ac_bits=7), 1, 0b11, ac_bits=7).tolist() == [[2040, -127]]
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_8bit_storage_loses_only_clamped_blocks(strong):
+    mask = oracle.prefix_mask(5)
+    pix = np.concatenate([_adversarial(), synth.image(8, 64, 1, 1, 4).numpy()], axis=2)
+    out = px.frag(pix, mask, strong, ac_bits=7)
+    back = px.defrag(pix.shape, mask, out["public"], out["private"], strong=strong, ac_bits=7)
+    clamped = (np.abs(out["q"][:, 1:]) > 127).any(axis=1)
+    same = (oracle.blocks_of(back) == oracle.blocks_of(pix)).all(axis=1)
+    assert np.all(same[~clamped]) and clamped.any() and not np.all(same[clamped])
+    # a clamped block is off by exactly R(stored) - R(exact), modulo 256
+    qs = px.stored_ints(out["q"], mask, 7)
+    d = (px.recon_private(qs, mask) - px.recon_private(out["q"], mask)) & 0xFF
+    got = (oracle.blocks_of(back).astype(np.int64) - oracle.blocks_of(pix).astype(np.int64)) & 0xFF
+    assert np.array_equal(got, d)
+
+
+def test_8bit_storage_exact_when_no_ac_exceeds_127():
+    # a low-contrast image (every private AC within 8-bit storage) comes back exactly
+    pix = (synth.image(64, 64, 1, 1, 2).numpy() // 4 + 96).astype(np.uint8)
+    mask = oracle.prefix_mask(5)
+    out = px.frag(pix, mask, True, ac_bits=7)
+    assert np.abs(out["q"][:, 1:]).max() <= 127
+    assert np.array_equal(px.defrag(pix.shape, mask, out["public"], out["private"], strong=True, ac_bits=7), pix)
