@@ -258,39 +258,46 @@ int dwt_defrag_image(uint32_t height, uint32_t width, uint32_t channels, const i
  * Figs. 6-8, Table 5).  desc as for frag_image with precision SF_FP32 (the
  * path is integer only) and at most 16 private coefficients (SF_ERANGE).
  *   private fragment: the private integers of frag_image (rule Q2, zigzag
- *     order), each in 11 bits: DC unsigned (0..2040), AC a sign bit (bit 10)
- *     above a 10-bit magnitude (|AC| <= 1020).  The fields of the blocks of a
- *     64-block tile form one little-endian bit stream, field j of block i of
- *     the tile at bit 11 (i P + j), P = private coefficients per block; tile
- *     t starts at byte t * S, S = 16 ceil(88 P / 16) (88 P bytes of fields,
- *     zero padding when P is odd); the last tile holds ceil(11 P n_t / 8)
- *     bytes.  The whole byte string is AES-128-CTR encrypted as in
- *     frag_image (aes NULL: plaintext).  12.9 % of the image for P = 6.
+ *     order), each in one field: DC unsigned in 11 bits (0..2040); AC a sign
+ *     bit above a 10-bit magnitude (11-bit storage, |AC| <= 1020, exact) or,
+ *     with SF_STORAGE_8BIT, above a 7-bit magnitude clamped to 127 (the
+ *     report's lossy 8-bit storage, Sec. 6.4.3, Table 5).  A block's fields
+ *     follow each other in a record of B bits (B = 11 P for 11-bit storage);
+ *     the records of a 64-block tile form one little-endian bit stream
+ *     (block i of the tile at bit B i); tile t starts at byte t * S,
+ *     S = 16 ceil(8 B / 16) (zero padding up to the AES-block boundary); the
+ *     last tile holds ceil(B n_t / 8) bytes.  The whole byte string is
+ *     AES-128-CTR encrypted as in frag_image (aes NULL: plaintext).  The
+ *     fields take 12.9 % of the image for P = 6 at 11 bits, 9.96 % at 8.
  *   public fragment: one byte per sample, same layout as the image:
  *     P(p) = (x(p) - R(p)) mod 256 with R(p) = floor((sum_j q_j
  *     rhe(2^16 B[n_j][p]) + 2^15) / 2^16), the integer inverse of the
  *     private part (rhe: round half to even).
  *     It stands for the inverse DCT of the remaining coefficients (private
  *     ones zeroed), which the report stores as bytes, and makes the round trip
- *     exact: x(p) = (R(p) + P(p)) mod 256.
- *   level SF_LEVEL_STRONG (Sec. 6.3.2, Fig. 8): the 64 public bytes of each
+ *     exact: x(p) = (R(p) + P(p)) mod 256.  P is always made from the exact
+ *     integers; with 8-bit storage defrag uses the stored (clamped) ones, so
+ *     blocks with a clamped AC come back as (x + R(stored) - R(exact)) mod 256.
+ *   flags SF_LEVEL_STRONG (Sec. 6.3.2, Fig. 8): the 64 public bytes of each
  *     block are XORed with the SHA-512 digest (FIPS 180-4) of the block's
- *     private integers as int16 little endian, digest byte 8y + x on sample
- *     (y, x) of the block.  SF_LEVEL_FIRST leaves them as they are.
+ *     stored private integers as int16 little endian, digest byte 8y + x on
+ *     sample (y, x) of the block.  SF_LEVEL_FIRST (0) leaves them as they are.
+ *     Flags combine with OR; frag and defrag must be given the same flags.
  * Buffers: device memory owned by the caller; pixels 8-byte aligned, public
  * and private 16-byte aligned (SF_EINVAL otherwise).  Kernels run on
  * stream; errors as for frag_image.
  * ------------------------------------------------------------------- */
 #define SF_LEVEL_FIRST 0
 #define SF_LEVEL_STRONG 1
+#define SF_STORAGE_8BIT 2
 
-/* Host only: public (C*H*W) and private fragment bytes. */
-int sf_pixel_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private_bytes);
+/* Host only: public (C*H*W) and private fragment bytes for these flags. */
+int sf_pixel_fragment_sizes(const sf_desc *desc, int flags, size_t *public_bytes, size_t *private_bytes);
 
-int pixel_frag_image(const sf_desc *desc, int level, const uint8_t *d_pixels, uint8_t *d_public,
+int pixel_frag_image(const sf_desc *desc, int flags, const uint8_t *d_pixels, uint8_t *d_public,
                      uint8_t *d_private, const sf_aes_ctr *aes, void *stream);
 
-int pixel_defrag_image(const sf_desc *desc, int level, const uint8_t *d_public, const uint8_t *d_private,
+int pixel_defrag_image(const sf_desc *desc, int flags, const uint8_t *d_public, const uint8_t *d_private,
                        const sf_aes_ctr *aes, uint8_t *d_pixels, void *stream);
 
 /* ---------------------------------------------------------------------

@@ -339,48 +339,49 @@ static int pixel_geom(const sf_desc *desc, Geom *g) {
   return SF_OK;
 }
 
-int sf_pixel_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private_bytes) {
+static int pixel_flags(int flags) {
+  if (flags & ~(SF_LEVEL_STRONG | SF_STORAGE_8BIT)) return fail(SF_EINVAL, "unknown pixel-format flags");
+  return SF_OK;
+}
+
+int sf_pixel_fragment_sizes(const sf_desc *desc, int flags, size_t *public_bytes, size_t *private_bytes) {
   Geom g;
   int rc = pixel_geom(desc, &g);
-  if (rc) return rc;
+  if (rc || (rc = pixel_flags(flags))) return rc;
+  const PixLayout l = pixel_layout(g, flags);
   if (public_bytes) *public_bytes = (size_t)g.nb * 64u;
-  if (private_bytes) *private_bytes = (size_t)(g.ntiles - 1u) * pixel_tile_stride(g.npriv) + pixel_last_tile_bytes(g);
+  if (private_bytes) *private_bytes = (size_t)(g.ntiles - 1u) * l.stride + l.last_bytes;
   return SF_OK;
 }
 
-static int pixel_level(int level) {
-  if (level != SF_LEVEL_FIRST && level != SF_LEVEL_STRONG) return fail(SF_EINVAL, "unknown protection level");
-  return SF_OK;
-}
-
-int pixel_frag_image(const sf_desc *desc, int level, const uint8_t *d_pixels, uint8_t *d_public, uint8_t *d_private,
+int pixel_frag_image(const sf_desc *desc, int flags, const uint8_t *d_pixels, uint8_t *d_public, uint8_t *d_private,
                      const sf_aes_ctr *aes, void *stream) {
   Geom g;
   int rc = pixel_geom(desc, &g);
-  if (rc || (rc = pixel_level(level))) return rc;
+  if (rc || (rc = pixel_flags(flags))) return rc;
   if (!d_pixels || !d_public || !d_private) return fail(SF_EINVAL, "NULL buffer");
   if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
   DeviceState *ds;
   if ((rc = device_state(&ds))) return rc;
   AesArgs a;
   make_aes_args(aes, &a);
-  rc = launch_pixel_frag(*ds, g, level == SF_LEVEL_STRONG, d_pixels, d_public, d_private, a, (hipStream_t)stream);
+  rc = launch_pixel_frag(*ds, g, flags, d_pixels, d_public, d_private, a, (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }
 
-int pixel_defrag_image(const sf_desc *desc, int level, const uint8_t *d_public, const uint8_t *d_private,
+int pixel_defrag_image(const sf_desc *desc, int flags, const uint8_t *d_public, const uint8_t *d_private,
                        const sf_aes_ctr *aes, uint8_t *d_pixels, void *stream) {
   Geom g;
   int rc = pixel_geom(desc, &g);
-  if (rc || (rc = pixel_level(level))) return rc;
+  if (rc || (rc = pixel_flags(flags))) return rc;
   if (!d_pixels || !d_public || !d_private) return fail(SF_EINVAL, "NULL buffer");
   if ((rc = check_alignment(d_pixels, d_public, d_private))) return rc;
   DeviceState *ds;
   if ((rc = device_state(&ds))) return rc;
   AesArgs a;
   make_aes_args(aes, &a);
-  rc = launch_pixel_defrag(*ds, g, level == SF_LEVEL_STRONG, d_public, d_private, a, d_pixels, (hipStream_t)stream);
+  rc = launch_pixel_defrag(*ds, g, flags, d_public, d_private, a, d_pixels, (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }

@@ -1,6 +1,7 @@
 // Pixel-domain fragment formats of the report: the private coefficients
 // stored in 11 bits each (Sec. 6.4.3: DC unsigned, AC sign + 10-bit
-// magnitude) and the public part stored as one byte per sample in the pixel
+// magnitude), or in the report's lossy 8-bit storage (AC sign + 7 bits,
+// clamped; DC 11 bits), and the public part stored as one byte per sample in the pixel
 // domain (Sec. 6.3.1, the inverse DCT of the remaining coefficients), with the
 // strong level of protection (Sec. 6.3.2, Fig. 8) as an option: the 64 public
 // bytes of a block XORed with the SHA-512 digest of its private integers.
@@ -45,6 +46,8 @@ struct PixArgs {
   const uint32_t *aes_t0;
   AesArgs aes;
   uint32_t np;          // private coefficients per block
+  uint32_t ac_bits;     // AC magnitude bits: 10 (11-bit fields) or 7 (8-bit fields)
+  uint32_t rec_bits;    // bits per block record
   uint32_t stride;      // bytes per full tile, multiple of 16
   uint32_t last_bytes;  // bytes of the last tile
   uint8_t nat[kPixMaxPriv];  // natural index of private coefficient j (zigzag order)
@@ -175,6 +178,12 @@ __device__ __forceinline__ cu32_ptr inv_table() {
   return (cu32_ptr)(ka + offsetof(PixArgs, inv)) + opaque_zero();
 }
 
+// Field j of a record: DC (j = 0 when DC is private) takes 11 bits, every AC
+// field ac_bits + 1 (sign above magnitude).
+__device__ __forceinline__ uint32_t field_offset(uint32_t j, uint32_t dc, uint32_t acw) {
+  return acw * j + (j > 0u ? dc * (kFieldBits - acw) : 0u);
+}
+
 __device__ __forceinline__ uint32_t tile_bytes(const PixArgs &a, uint32_t t) {
   return t + 1u == a.g.ntiles ? a.last_bytes : a.stride;
 }
@@ -228,25 +237,34 @@ __global__ __launch_bounds__(kThreads) void pixel_frag_kernel(PixArgs a) {
         else q[j] = q2_round(q2_mfma_acc(stage, (uint32_t)j - dc, lane));
       }
     }
-    // 11-bit fields into the tile's bit stream (zeroed above)
+    // the public part uses the exact integers (packed in pairs for the
+    // inverse); the fields and the strong-level hash hold the stored ones
+    uint32_t qp[kPixMaxPriv / 2];
+#pragma unroll
+    for (int i = 0; i < kPixMaxPriv / 2; ++i) qp[i] = ((uint32_t)q[2 * i] & 0xffffu) | ((uint32_t)q[2 * i + 1] << 16);
+    const int32_t lim = (1 << a.ac_bits) - 1;  // never reached at 10 bits (|AC| <= 1020)
+#pragma unroll
+    for (int j = 0; j < kPixMaxPriv; ++j) {
+      const int n = NP > 0 ? kZigZag.nat[j < 64 ? j : 0] : (int)a.nat[j];
+      if (n != 0) q[j] = max(-lim, min(lim, q[j]));
+    }
+    // fields into the tile's bit stream (zeroed above)
     if (valid) {
-      const uint32_t base = (uint32_t)lane * kFieldBits * np;
+      const uint32_t base = (uint32_t)lane * a.rec_bits;
+      const uint32_t acw = a.ac_bits + 1u;
 #pragma unroll
       for (int j = 0; j < kPixMaxPriv; ++j) {
         if (NP > 0 ? j < NP : (uint32_t)j < np) {
           const int n = NP > 0 ? kZigZag.nat[j < 64 ? j : 0] : (int)a.nat[j];
           const uint32_t mag = (uint32_t)(q[j] < 0 ? -q[j] : q[j]);
-          const uint32_t fld = n == 0 ? (uint32_t)q[j] : (mag | (q[j] < 0 ? 0x400u : 0u));
-          const uint32_t pos = base + kFieldBits * (uint32_t)j;
+          const uint32_t fld = n == 0 ? (uint32_t)q[j] : (mag | (q[j] < 0 ? 1u << a.ac_bits : 0u));
+          const uint32_t pos = base + field_offset((uint32_t)j, dc, acw);
           const uint64_t v = (uint64_t)fld << (pos & 31u);
           atomicOr(&lw[pos >> 5], (uint32_t)v);
           if ((uint32_t)(v >> 32)) atomicOr(&lw[(pos >> 5) + 1u], (uint32_t)(v >> 32));
         }
       }
     }
-    uint32_t qp[kPixMaxPriv / 2];
-#pragma unroll
-    for (int i = 0; i < kPixMaxPriv / 2; ++i) qp[i] = ((uint32_t)q[2 * i] & 0xffffu) | ((uint32_t)q[2 * i + 1] << 16);
     uint64_t Hm[8];
     if constexpr (kStrong) sha512_private<NP>(q, np, Hm);
     if (valid) {
@@ -285,6 +303,7 @@ __global__ __launch_bounds__(kThreads) void pixel_defrag_kernel(PixArgs a) {
   const TileGeom &g = a.g;
   const uint32_t np = NP > 0 ? (uint32_t)NP : a.np;
   const uint32_t npair = (np + 1u) / 2u;
+  const uint32_t dc = NP > 0 ? 1u : (uint32_t)(g.mask & 1u);
   constexpr int kNPair = NP > 0 ? (NP + 1) / 2 : 0;
   for (uint32_t t = blockIdx.x * kWaves + wave; t < g.ntiles; t += gridDim.x * kWaves) {
     const TileLane L = tile_lane(g, t, lane);
@@ -307,17 +326,18 @@ __global__ __launch_bounds__(kThreads) void pixel_defrag_kernel(PixArgs a) {
                   a.aes.ctr_lo, (uint64_t)t * (a.stride / 16u));
     wave_lds_sync();
     int32_t q[kPixMaxPriv];
-    const uint32_t base = (uint32_t)lane * kFieldBits * np;
+    const uint32_t base = (uint32_t)lane * a.rec_bits;
+    const uint32_t acw = a.ac_bits + 1u;
 #pragma unroll
     for (int j = 0; j < kPixMaxPriv; ++j) {
       q[j] = 0;
       if (NP > 0 ? j < NP : (uint32_t)j < np) {
         const int n = NP > 0 ? kZigZag.nat[j < 64 ? j : 0] : (int)a.nat[j];
-        const uint32_t pos = base + kFieldBits * (uint32_t)j;
+        const uint32_t pos = base + field_offset((uint32_t)j, dc, acw);
         const uint64_t v = (uint64_t)lw[pos >> 5] | ((uint64_t)lw[(pos >> 5) + 1u] << 32);
-        const uint32_t fld = (uint32_t)(v >> (pos & 31u)) & 0x7ffu;
-        const int32_t mag = (int32_t)(fld & 0x3ffu);
-        const int32_t val = n == 0 ? (int32_t)fld : ((fld & 0x400u) ? -mag : mag);
+        const uint32_t raw = (uint32_t)(v >> (pos & 31u));
+        const int32_t mag = (int32_t)(raw & ((1u << a.ac_bits) - 1u));
+        const int32_t val = n == 0 ? (int32_t)(raw & 0x7ffu) : (((raw >> a.ac_bits) & 1u) ? -mag : mag);
         q[j] = valid ? val : 0;
       }
     }
@@ -372,8 +392,9 @@ void launch_one(bool frag, bool strong, const PixArgs &a, int grid, hipStream_t 
   }
 }
 
-int launch_pixel(const DeviceState &ds, const Geom &g, bool frag, bool strong, const uint8_t *pix, uint8_t *pub,
+int launch_pixel(const DeviceState &ds, const Geom &g, bool frag, int flags, const uint8_t *pix, uint8_t *pub,
                  uint8_t *priv, uint8_t *pix_out, const AesArgs &aes, hipStream_t stream) {
+  const bool strong = (flags & SF_LEVEL_STRONG) != 0;
   PixArgs a{};
   a.g = tile_geom(g, pix);
   a.pub = pub;
@@ -383,8 +404,11 @@ int launch_pixel(const DeviceState &ds, const Geom &g, bool frag, bool strong, c
   a.aes_t0 = ds.d_aes_t0;
   a.aes = aes;
   a.np = g.npriv;
-  a.stride = pixel_tile_stride(g.npriv);
-  a.last_bytes = pixel_last_tile_bytes(g);
+  const PixLayout lay = pixel_layout(g, flags);
+  a.ac_bits = lay.ac_bits;
+  a.rec_bits = lay.rec_bits;
+  a.stride = lay.stride;
+  a.last_bytes = lay.last_bytes;
   const HostTables &ht = host_tables();
   static constexpr ZigZag zz{};
   int j = 0;
@@ -409,21 +433,25 @@ int launch_pixel(const DeviceState &ds, const Geom &g, bool frag, bool strong, c
 
 }  // namespace
 
-uint32_t pixel_tile_stride(uint32_t np) { return 16u * ((88u * np + 15u) / 16u); }
-
-uint32_t pixel_last_tile_bytes(const Geom &g) {
+PixLayout pixel_layout(const Geom &g, int flags) {
+  PixLayout l;
+  l.ac_bits = (flags & SF_STORAGE_8BIT) ? 7u : 10u;
+  const uint32_t dc = (uint32_t)(g.mask & 1u);
+  l.rec_bits = (l.ac_bits + 1u) * g.npriv + dc * (kFieldBits - (l.ac_bits + 1u));
+  l.stride = 16u * ((8u * l.rec_bits + 15u) / 16u);
   const uint64_t nt_last = g.nb - 64ull * (g.ntiles - 1u);
-  return (uint32_t)((kFieldBits * g.npriv * nt_last + 7u) / 8u);
+  l.last_bytes = (uint32_t)((l.rec_bits * nt_last + 7u) / 8u);
+  return l;
 }
 
-int launch_pixel_frag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pix, uint8_t *pub,
+int launch_pixel_frag(const DeviceState &ds, const Geom &g, int flags, const uint8_t *pix, uint8_t *pub,
                       uint8_t *priv, const AesArgs &aes, hipStream_t stream) {
-  return launch_pixel(ds, g, true, strong, pix, pub, priv, nullptr, aes, stream);
+  return launch_pixel(ds, g, true, flags, pix, pub, priv, nullptr, aes, stream);
 }
 
-int launch_pixel_defrag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pub, const uint8_t *priv,
+int launch_pixel_defrag(const DeviceState &ds, const Geom &g, int flags, const uint8_t *pub, const uint8_t *priv,
                         const AesArgs &aes, uint8_t *pix, hipStream_t stream) {
-  return launch_pixel(ds, g, false, strong, nullptr, const_cast<uint8_t *>(pub), const_cast<uint8_t *>(priv), pix,
+  return launch_pixel(ds, g, false, flags, nullptr, const_cast<uint8_t *>(pub), const_cast<uint8_t *>(priv), pix,
                       aes, stream);
 }
 

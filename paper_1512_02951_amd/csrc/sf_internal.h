@@ -110,11 +110,16 @@ int launch_dwt_defrag(const DeviceState &ds, const Geom &g, const int16_t *pub, 
 // Pixel-domain formats: 11-bit private fields, byte public part, optional
 // SHA-512 strong level (pixel.hip).  At most kPixMaxPriv private coefficients.
 constexpr int kPixMaxPriv = 16;
-uint32_t pixel_tile_stride(uint32_t np);
-uint32_t pixel_last_tile_bytes(const Geom &g);
-int launch_pixel_frag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pix, uint8_t *pub,
+struct PixLayout {
+  uint32_t ac_bits;     // 10 (11-bit fields) or 7 (8-bit fields)
+  uint32_t rec_bits;    // bits per block
+  uint32_t stride;      // bytes per full tile (multiple of 16)
+  uint32_t last_bytes;  // bytes of the last tile
+};
+PixLayout pixel_layout(const Geom &g, int flags);
+int launch_pixel_frag(const DeviceState &ds, const Geom &g, int flags, const uint8_t *pix, uint8_t *pub,
                       uint8_t *priv, const AesArgs &aes, hipStream_t stream);
-int launch_pixel_defrag(const DeviceState &ds, const Geom &g, bool strong, const uint8_t *pub, const uint8_t *priv,
+int launch_pixel_defrag(const DeviceState &ds, const Geom &g, int flags, const uint8_t *pub, const uint8_t *priv,
                         const AesArgs &aes, uint8_t *pix, hipStream_t stream);
 
 // Security statistics (stats.hip).

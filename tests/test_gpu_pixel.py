@@ -24,18 +24,23 @@ def _adversarial():
     return np.concatenate([b.astype(np.uint8) for b in blocks], axis=1)[None]
 
 
-def _check(x, mask, strong, key=None, ctr0=None, label=""):
-    print("case:", label, x.shape, hex(mask), strong, key is not None, flush=True)
+def _check(x, mask, strong, key=None, ctr0=None, label="", storage_bits=11):
+    print("case:", label, x.shape, hex(mask), strong, key is not None, storage_bits, flush=True)
+    ac_bits = 10 if storage_bits == 11 else 7
     xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
-    fr = pixel.pixel_frag_image(xd, mask, strong, key, ctr0)
+    fr = pixel.pixel_frag_image(xd, mask, strong, key, ctr0, storage_bits=storage_bits)
     y = pixel.pixel_defrag_image(fr, key, ctr0)
     torch.cuda.synchronize()
-    ref = opx.frag(x, mask, strong, key, ctr0)
+    ref = opx.frag(x, mask, strong, key, ctr0, ac_bits=ac_bits)
     assert np.array_equal(fr.public.cpu().numpy(), ref["public"]), "public bytes differ"
     n = ref["private"].size
+    assert pixel.fragment_sizes(*x.shape[1:], x.shape[0], mask, strong, storage_bits)[1] == n
     want = ref["cipher"] if key is not None else ref["private"]
     assert np.array_equal(fr.private.cpu().numpy()[:n], want), "private bytes differ"
-    assert torch.equal(y.cpu(), torch.from_numpy(x)), "round trip differs"
+    back = opx.defrag(x.shape, mask, ref["public"], ref["private"], strong=strong, ac_bits=ac_bits)
+    assert np.array_equal(y.cpu().numpy(), back), "restored image differs from the oracle's"
+    if storage_bits == 11:
+        assert torch.equal(y.cpu(), torch.from_numpy(x)), "round trip differs"
 
 
 MASKS = [1, 0x7, 0x3f, 0x3ff, 0b1011000100101110, (1 << 16) - 2, (1 << 16) - 1, 0b11]
@@ -46,6 +51,16 @@ MASKS = [1, 0x7, 0x3f, 0x3ff, 0b1011000100101110, (1 << 16) - 2, (1 << 16) - 1, 
 def test_masks_adversarial_and_synthetic(mask, strong):
     x = np.concatenate([_adversarial(), synth.image(8, 64, 1, 1, 6).numpy()], axis=2)
     _check(x, mask, strong, synth.aes_key(1), synth.ctr0(1, 6), "masks")
+
+
+@pytest.mark.parametrize("mask", [0x7, 0x3f, 0x3ff, (1 << 16) - 2, 0b1011000100101110])
+@pytest.mark.parametrize("strong", [False, True])
+def test_8bit_storage(mask, strong):
+    # the report's lossy storage: bit-exact against the oracle, including the
+    # restored image (exact except where an AC was clamped)
+    x = np.concatenate([_adversarial(), synth.image(8, 64, 1, 1, 6).numpy()], axis=2)
+    _check(x, mask, strong, synth.aes_key(1), synth.ctr0(1, 6), "8-bit", storage_bits=8)
+    _check(synth.image(72, 136, 3, 2, 5).numpy(), mask, strong, None, None, "8-bit ragged", storage_bits=8)
 
 
 @pytest.mark.parametrize("shape", [(1, 8, 8), (3, 24, 40), (1, 72, 136), (2, 64, 512), (1, 8, 4104)])
@@ -95,3 +110,4 @@ def test_errors():
         pixel.pixel_frag_image(torch.zeros((1, 12, 16), dtype=torch.uint8, device="cuda"), 0x3f)
     assert e.value.code == sf.SF_ESHAPE
     assert pixel.fragment_sizes(16, 16, 1, 0x3f) == (256, 33)
+    assert pixel.fragment_sizes(16, 16, 1, 0x3f, storage_bits=8) == (256, (51 * 4 + 7) // 8)
