@@ -34,18 +34,15 @@ def algorithmic_bytes(H, W, C, npriv, pub_elt=4):
 PROFILE = os.path.join(ROOT, "profiles", "frag_defrag_4096rgb_k5.md")
 
 
-def source_sha1():
-    """Hash of the sources the headline frag / defrag kernels are compiled
-    from (their translation unit, its headers and the constant tables)."""
-    import hashlib
-    h = hashlib.sha1()
-    csrc = os.path.join(ROOT, "paper_1512_02951_amd", "csrc")
-    files = [os.path.join(csrc, n) for n in ("plain.hip", "plain_tile.h", "sf_device.h", "sf_internal.h", "tables.hip")]
-    for f in files + [os.path.join(ROOT, "include", "sefrag.h")]:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+def code_sha1():
+    """Fingerprint of the compiled headline frag / defrag kernels: the SHA-1 of
+    the machine code and kernel descriptors of their translation unit, written
+    by the build next to the library (None if it is missing)."""
+    try:
+        with open(os.path.join(ROOT, "paper_1512_02951_amd", "kernel_code_sha1.json")) as f:
+            return json.load(f).get("plain.hip")
+    except (OSError, ValueError):
+        return None
 
 
 def measured_traffic(kernel: str):
@@ -57,7 +54,8 @@ def measured_traffic(kernel: str):
     except (OSError, IndexError):
         return None
     fields = dict(kv.split("=") for kv in line.split()[1:])
-    if fields.get("source_sha1") != source_sha1():
+    code = code_sha1()
+    if code is None or fields.get("code_sha1") != code:
         return None
     return int(fields[kernel]) if kernel in fields else None
 

@@ -5,6 +5,7 @@ Run ``python -m paper_1512_02951_amd.build`` (or ``__graft_entry__.build()``).
 from __future__ import annotations
 
 import glob
+import json
 import os
 import shutil
 import subprocess
@@ -55,6 +56,45 @@ def _run(cmd, verbose):
             sys.stderr.write("\n".join(lines) + "\n")
 
 
+CODE_HASH = os.path.join(PKG, "kernel_code_sha1.json")
+# translation units whose machine code is fingerprinted at build time
+HASHED_UNITS = ("plain.hip",)
+
+
+def _llvm_tool(name):
+    for d in ("/opt/rocm/llvm/bin", os.path.dirname(hipcc())):
+        p = os.path.join(d, name)
+        if os.path.exists(p):
+            return p
+    return shutil.which(name)
+
+
+def code_sha1(obj: str) -> str | None:
+    """SHA-1 of the .text and .rodata sections (instructions and kernel
+    descriptors) of the gfx950 code object inside a compiled object file.
+    Unlike a hash of the sources it changes only when the generated code does."""
+    import hashlib
+    tools = [_llvm_tool(n) for n in ("llvm-objcopy", "clang-offload-bundler")]
+    if not all(tools):
+        return None
+    objcopy, bundler = tools
+    with tempfile.TemporaryDirectory(prefix="sefrag_hash_") as d:
+        fat, co = os.path.join(d, "fat.bin"), os.path.join(d, "code.o")
+        steps = [[objcopy, "--dump-section=.hip_fatbin=" + fat, obj, os.path.join(d, "host.o")],
+                 [bundler, "--unbundle", "--type=o", "--input=" + fat,
+                  "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--output=" + co]]
+        for sec in (".text", ".rodata"):
+            steps.append([objcopy, "-O", "binary", "--only-section=" + sec, co, os.path.join(d, sec[1:])])
+        for cmd in steps:
+            if subprocess.run(cmd, capture_output=True).returncode != 0:
+                return None
+        h = hashlib.sha1()
+        for sec in ("text", "rodata"):
+            with open(os.path.join(d, sec), "rb") as f:
+                h.update(f.read())
+        return h.hexdigest()
+
+
 def build(verbose: bool = False, extra=(), out: str | None = None, jobs: int | None = None) -> str:
     """Compile every HIP source (in parallel) and link libsefrag.so; always
     recompiles.  ``extra`` adds compiler flags (e.g. -D tuning knobs); ``out``
@@ -69,7 +109,12 @@ def build(verbose: bool = False, extra=(), out: str | None = None, jobs: int | N
         with ThreadPoolExecutor(jobs) as pool:
             list(pool.map(lambda c: _run(c, verbose), cmds))
         _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+        hashes = {os.path.basename(src): code_sha1(o) for src, o in zip(sources(), objs)
+                  if os.path.basename(src) in HASHED_UNITS}
     os.replace(tmp, lib)
+    if out is None:
+        with open(CODE_HASH, "w") as f:
+            json.dump(hashes, f, indent=1, sort_keys=True)
     return lib
 
 
