@@ -103,3 +103,10 @@ def test_error_strings():
     L = sf.lib()
     for code in (sf.SF_OK, sf.SF_EINVAL, sf.SF_ESHAPE, sf.SF_ERANGE, sf.SF_EHIP, sf.SF_ENOTSUP):
         assert L.sf_strerror(code)
+
+
+def test_c_consumer_builds_against_the_header(tmp_path):
+    # a plain C program (tests/c_abi_roundtrip.c) compiles and links against
+    # include/sefrag.h and the in-tree library; the GPU test runs it
+    from c_abi_build import build_c_program
+    assert os.path.exists(build_c_program(str(tmp_path)))
