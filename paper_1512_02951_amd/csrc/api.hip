@@ -401,7 +401,7 @@ int sf_security_stats_compute(const uint8_t *d_x, const uint8_t *d_y, uint32_t H
   DeviceState *ds;
   int rc = device_state(&ds);
   if (rc) return rc;
-  rc = launch_security_stats(d_x, d_y, H, W, C, d_ws, d_out, d_block_entropy, (hipStream_t)stream);
+  rc = launch_security_stats(*ds, d_x, d_y, H, W, C, d_ws, d_out, d_block_entropy, (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }

@@ -124,8 +124,8 @@ int launch_pixel_defrag(const DeviceState &ds, const Geom &g, int flags, const u
 
 // Security statistics (stats.hip).
 size_t stats_workspace_bytes();
-int launch_security_stats(const uint8_t *x, const uint8_t *y, uint32_t H, uint32_t W, uint32_t C, void *ws,
-                          sf_security_stats *out, float *block_entropy, hipStream_t stream);
+int launch_security_stats(const DeviceState &ds, const uint8_t *x, const uint8_t *y, uint32_t H, uint32_t W,
+                          uint32_t C, void *ws, sf_security_stats *out, float *block_entropy, hipStream_t stream);
 
 // Differentiation form (softmask.hip).
 size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, uint32_t W);

@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kBandWaves = 4;
 constexpr int kBandThreads = 64 * kBandWaves;
-constexpr int kBandGrid = 1024;  // fixed: the partial slots are per workgroup
+constexpr int kBandGrid = 1024;  // the most band workgroups: one partial slot each
 constexpr uint32_t kFlushBands = 256;
 constexpr int kJointThreads = 1024;
 constexpr uint32_t kHalfBins = 32768;
@@ -155,15 +155,14 @@ __device__ __forceinline__ double band_block_count_product(const uint32_t (&w)[9
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // one row at a time (sched_barrier): all 32 accesses in flight at once
   // would hold twice the registers for no gain
-  // counter word of value v: (v / 4 + block) mod 64, so that lanes holding the
-  // same value (smooth regions) hit different LDS banks
-  const uint32_t rot = (uint32_t)(lane >> 1);
+  // counter of value v: byte v of the block's 256-byte array
+  uint8_t *bytes_w = reinterpret_cast<uint8_t *>(blk);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t v = (w[r] >> (8 * i)) & 0xffu;
-      atomicAdd(&blk[((v >> 2) + rot) & 63u], 1u << (8 * (v & 3u)));
+      atomicAdd(reinterpret_cast<uint32_t *>(bytes_w + (v & 0xfcu)), 1u << ((v & 3u) << 3));
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -178,10 +177,7 @@ __device__ __forceinline__ double band_block_count_product(const uint32_t (&w)[9
   for (int r = 0; r < 8; ++r) {
     uint32_t q = 1u;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t v = (w[r] >> (8 * i)) & 0xffu;
-      q *= bytes[4u * (((v >> 2) + rot) & 63u) + (v & 3u)];
-    }
+    for (int i = 0; i < 4; ++i) q *= bytes[(w[r] >> (8 * i)) & 0xffu];
     p *= (double)q;
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -561,8 +557,8 @@ static_assert(kHistBytes % 16 == 0 && kPartBytes % 16 == 0, "workspace parts sta
 
 size_t stats_workspace_bytes() { return kHistBytes + kPartBytes + sizeof(Reduced); }
 
-int launch_security_stats(const uint8_t *x, const uint8_t *y, uint32_t H, uint32_t W, uint32_t C, void *ws,
-                          sf_security_stats *out, float *block_entropy, hipStream_t stream) {
+int launch_security_stats(const DeviceState &ds, const uint8_t *x, const uint8_t *y, uint32_t H, uint32_t W,
+                          uint32_t C, void *ws, sf_security_stats *out, float *block_entropy, hipStream_t stream) {
   const StatsGeom g = stats_geom(H, W, C);
   uint32_t *hist = static_cast<uint32_t *>(ws);
   Partial *parts = reinterpret_cast<Partial *>(static_cast<uint8_t *>(ws) + kHistBytes);
@@ -573,15 +569,25 @@ int launch_security_stats(const uint8_t *x, const uint8_t *y, uint32_t H, uint32
   hipLaunchKernelGGL(stats_clear_kernel, dim3(1), dim3(256), 0, stream, reinterpret_cast<uint32_t *>(red->hy),
                      (uint32_t)(sizeof(red->hy) / 4));
   BandArgs b{g, x, y, parts, block_entropy};
+  // one generation of resident workgroups (more would leave a partly empty
+  // last generation), at most kBandGrid partial slots
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)&stats_band_kernel, kBandThreads, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
   const uint32_t need = (g.nbands + kBandWaves - 1) / kBandWaves;
-  const uint32_t grid = need < (uint32_t)kBandGrid ? need : (uint32_t)kBandGrid;
+  uint32_t grid = std::min<uint32_t>((uint32_t)ds.num_cu * (uint32_t)per_cu, (uint32_t)kBandGrid);
+  grid = std::min(grid, need);
   // unused partial slots are read by the finalize kernel: it takes only `grid`
   hipLaunchKernelGGL(stats_band_kernel, dim3(grid), dim3(kBandThreads), 0, stream, b);
   JointArgs j;
   j.x = reinterpret_cast<const uint4 *>(x);
   j.y = reinterpret_cast<const uint4 *>(y);
   j.nvec = (uint64_t)C * H * W / 16u;
-  const uint64_t chunks = std::max<uint64_t>(1, std::min<uint64_t>(256, j.nvec / 16384u));
+  // 128 KB of LDS: one workgroup per CU; two per chunk (the halves), so
+  // num_cu / 2 chunks fill the chip in one generation
+  const uint64_t chunks = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ds.num_cu / 2u, j.nvec / 16384u));
   j.per_chunk = (j.nvec + chunks - 1) / chunks;
   j.hist = hist;
   hipLaunchKernelGGL(stats_joint_kernel, dim3((uint32_t)chunks, 2), dim3(kJointThreads), 0, stream, j);
