@@ -14,10 +14,15 @@ Contents
 * The soft frequency-mask objective in FP64 (numpy): public image
   P = IDCT(DCT(x) * (1 - sigmoid(l))) following the zero-padded public image of
   Sec. 6.3.1/Fig. 7, Pearson correlation of Sec. 6.6.2, loss and gradient.
+* ``oracle.dwt``: the LeGall 5/3 wavelet variant (Sec. 6.8-6.9, Eqs. (1)-(2)).
+* ``oracle.pixel``: the report's storage formats (11-bit and 8-bit private
+  fields, public bytes in the pixel domain) and the SHA-512 strong level
+  (Sec. 6.3.2, 6.4.3).
+* ``oracle.stats``: the security statistics of Sec. 6.6 and 6.10.
 
 Every function is pinned in ``tests/test_oracle_*.py`` against something other
-than itself (closed forms, scipy, published AES/CTR vectors, openssl,
-mpmath, brute force, finite differences).
+than itself (closed forms, scipy, published AES/CTR and SHA-512 vectors,
+openssl, mpmath, brute force, finite differences, values the report prints).
 """
 from __future__ import annotations
 
