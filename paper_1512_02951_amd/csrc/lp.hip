@@ -85,6 +85,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 
+// Waves per frag workgroup.  fp16 frag with a compile-time selection fits in
+// 128 VGPRs (4 waves per SIMD), but the LDS of 4-wave workgroups admits only 3
+// per CU; 8-wave workgroups fit 2 per CU, 16 waves.  The extra waves also even
+// out the last round of tiles (an 8192^2 image: 4 tiles per wave instead of
+// 5.33).  Every other kernel keeps 4-wave workgroups: measured, bf16 at 12
+// waves per CU (6-wave workgroups) and fp16 defrag at 8 (8-wave workgroups,
+// one per CU) ran 15-30 % slower than at their 8 and 12.
+template <bool BF, class MP>
+constexpr int frag_waves() {
+  return (!BF && MP::kStatic) ? 8 : kWaves;
+}
+
 template <bool BF>
 __device__ __forceinline__ f32x16 mfma(const uint4 &a, const uint4 &b, const f32x16 &c) {
   if constexpr (BF)
@@ -203,10 +215,10 @@ struct LpDefragArgs {
 };
 
 template <bool BF>
-__device__ __forceinline__ void load_lp_tables(LpLds<BF> &L, const uint32_t *tables, int tid) {
+__device__ __forceinline__ void load_lp_tables(LpLds<BF> &L, const uint32_t *tables, int tid, int nthreads) {
   const uint4 *src = reinterpret_cast<const uint4 *>(tables);
   constexpr int kWords4 = kLpTableWords / 4;  // uint4 per table
-  for (int i = tid; i < kWords4; i += kThreads) {
+  for (int i = tid; i < kWords4; i += nthreads) {
     if constexpr (BF) {
       L.t[0][i] = src[2 * kWords4 + i];
       L.t[1][i] = src[3 * kWords4 + i];
@@ -379,7 +391,8 @@ __device__ __forceinline__ void lp_pixel_rows(const uint2 (&prow)[4], uint32_t (
 }
 
 template <bool BF, class MP, bool kQ2Mfma>
-__global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void frag_lp_kernel(LpFragArgs a) {
+__global__ __launch_bounds__(64 * (frag_waves<BF, MP>()), MP::kStatic ? 3 : 2) void frag_lp_kernel(LpFragArgs a) {
+  constexpr uint32_t nw = frag_waves<BF, MP>();
   __shared__ AesLds s_aes;
   __shared__ LpLds<BF> s_tab;
   __shared__ Q2Operands s_q2[kQ2Mfma ? 64 : 1];
@@ -387,8 +400,8 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void frag_lp_kernel(
   const int lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const TileGeom &g = a.g;
-  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
-  load_lp_tables<BF>(s_tab, a.tables, threadIdx.x);
+  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, 64 * nw);
+  load_lp_tables<BF>(s_tab, a.tables, threadIdx.x, 64 * nw);
   if constexpr (kQ2Mfma)
     if (threadIdx.x < 64) s_q2[lane] = q2_operands(a.q2, private_ac<MP>(g.mask, lane & 15), lane);
   __syncthreads();
@@ -396,10 +409,10 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void frag_lp_kernel(
   uint8_t *stage = lp + a.lds_priv_bytes;
   const uint64_t mask = MP::kStatic ? g.mask : opaque_u64(g.mask);
   const uint32_t h = (uint32_t)lane >> 5, jl = (uint32_t)lane & 31u;
-  const uint32_t stride = gridDim.x * kWaves;
+  const uint32_t stride = gridDim.x * nw;
   uint32_t rflag = 0;
 
-  uint32_t t = blockIdx.x * kWaves + wave;
+  uint32_t t = blockIdx.x * nw + wave;
   TileLane Lnext = tile_lane(g, t < g.ntiles ? t : 0u, lane);
   uint32_t xs[16];
   if (t < g.ntiles) load_block(g, Lnext, xs);
@@ -555,7 +568,7 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void defrag_lp_kerne
   const int lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
-  load_lp_tables<BF>(s_tab, a.tables, threadIdx.x);
+  load_lp_tables<BF>(s_tab, a.tables, threadIdx.x, kThreads);
   __syncthreads();
   uint8_t *lp = s_dyn + wave * (a.lds_priv_bytes + kLpStage);
   uint8_t *stage = lp + a.lds_priv_bytes;
@@ -615,11 +628,11 @@ __global__ __launch_bounds__(kThreads, MP::kStatic ? 3 : 2) void defrag_lp_kerne
 
 uint32_t lds_priv_bytes(const Geom &g) { return (2u * g.npriv * 64u + 15u) & ~15u; }
 
-int grid_for(const DeviceState &ds, const void *kernel, size_t lds, uint32_t ntiles) {
+int grid_for(const DeviceState &ds, const void *kernel, int waves, size_t lds, uint32_t ntiles) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * waves, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
-  const uint32_t need = (ntiles + kWaves - 1) / kWaves;
+  const uint32_t need = (ntiles + waves - 1) / waves;
   const uint32_t cap = (uint32_t)ds.num_cu * (uint32_t)per_cu;
   return (int)(need < cap ? need : cap);
 }
@@ -634,10 +647,11 @@ int lds_fits(const DeviceState &ds, size_t dynamic) {
 
 template <bool BF, class MP, bool kQ2Mfma>
 int launch_frag(const DeviceState &ds, const LpFragArgs &a, hipStream_t stream) {
-  const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + kLpStage);
+  constexpr int nw = frag_waves<BF, MP>();
+  const size_t lds = (size_t)nw * (a.lds_priv_bytes + kLpStage);
   if (int rc = lds_fits<BF>(ds, lds)) return rc;
-  const int grid = grid_for(ds, (const void *)&frag_lp_kernel<BF, MP, kQ2Mfma>, lds, a.g.ntiles);
-  hipLaunchKernelGGL((frag_lp_kernel<BF, MP, kQ2Mfma>), dim3(grid), dim3(kThreads), lds, stream, a);
+  const int grid = grid_for(ds, (const void *)&frag_lp_kernel<BF, MP, kQ2Mfma>, nw, lds, a.g.ntiles);
+  hipLaunchKernelGGL((frag_lp_kernel<BF, MP, kQ2Mfma>), dim3(grid), dim3(64 * nw), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "frag_lp kernel launch");
 }
@@ -646,7 +660,7 @@ template <bool BF, class MP>
 int launch_defrag(const DeviceState &ds, const LpDefragArgs &a, hipStream_t stream) {
   const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + kLpStage);
   if (int rc = lds_fits<BF>(ds, lds)) return rc;
-  const int grid = grid_for(ds, (const void *)&defrag_lp_kernel<BF, MP>, lds, a.g.ntiles);
+  const int grid = grid_for(ds, (const void *)&defrag_lp_kernel<BF, MP>, kWaves, lds, a.g.ntiles);
   hipLaunchKernelGGL((defrag_lp_kernel<BF, MP>), dim3(grid), dim3(kThreads), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "defrag_lp kernel launch");
