@@ -60,6 +60,15 @@ __device__ __forceinline__ int32_t dot2(uint32_t a, uint32_t b, int32_t c) {
   return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), c, false);
 }
 
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+// A 64-bit word from its halves as a register pair.  Written as
+// (hi << 32) | lo, a sum of such words compiles to one add per half (the OR
+// of disjoint bits becomes an add and is reassociated) plus a move.
+__device__ __forceinline__ uint64_t pair64(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(uint64_t, u32x2_t{lo, hi});
+}
+
 // 64-bit rotate right by a constant, as two v_alignbit_b32 on the halves.
 template <int N>
 __device__ __forceinline__ uint64_t rotr64(uint64_t x) {
@@ -71,17 +80,56 @@ __device__ __forceinline__ uint64_t rotr64(uint64_t x) {
   }
   constexpr uint32_t n = N & 31;
   const uint32_t nlo = __builtin_amdgcn_alignbit(hi, lo, n), nhi = __builtin_amdgcn_alignbit(lo, hi, n);
-  return ((uint64_t)nhi << 32) | nlo;
+  return pair64(nlo, nhi);
 }
 
 __device__ __forceinline__ uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c) {
-  return ((uint64_t)xor3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32) |
-         xor3((uint32_t)a, (uint32_t)b, (uint32_t)c);
+  return pair64(xor3((uint32_t)a, (uint32_t)b, (uint32_t)c), xor3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)));
+}
+
+// Bitwise majority of three 64-bit words, one v_bitop3_b32 per half (truth
+// table 0xE8: set where at least two inputs are set; symmetric in its inputs).
+// Written as ANDs and XORs it compiles to four instructions per half.
+__device__ __forceinline__ uint64_t maj3_64(uint64_t a, uint64_t b, uint64_t c) {
+  const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0xE8);
+  const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0xE8);
+  return pair64(lo, hi);
+}
+
+// Round constants as scalar-loadable memory for the rolled rounds 16..79.
+struct Sha512Table {
+  uint64_t k[80];
+};
+constexpr Sha512Table sha512_table() {
+  Sha512Table t{};
+  for (int i = 0; i < 80; ++i) t.k[i] = kSha512K[i];
+  return t;
+}
+__constant__ Sha512Table c_sha512 = sha512_table();
+
+// One SHA-512 round (FIPS 180-4, Sec. 6.4.2) on the working variables v[0..7]
+// = a..h, addressed so that round t reads a at v[(8 - t % 8) % 8]: the
+// variables rotate by renaming, never by moves.
+template <int R>
+__device__ __forceinline__ void sha512_round(uint64_t (&v)[8], uint64_t kw) {
+  constexpr int o = (8 - (R & 7)) & 7;
+  uint64_t &a = v[o], &b = v[(o + 1) & 7], &c = v[(o + 2) & 7], &d = v[(o + 3) & 7];
+  uint64_t &e = v[(o + 4) & 7], &f = v[(o + 5) & 7], &g = v[(o + 6) & 7], &h = v[(o + 7) & 7];
+  const uint64_t S1 = xor3_64(rotr64<14>(e), rotr64<18>(e), rotr64<41>(e));
+  const uint64_t ch = (e & f) ^ (~e & g);
+  const uint64_t t1 = h + S1 + ch + kw;
+  const uint64_t S0 = xor3_64(rotr64<28>(a), rotr64<34>(a), rotr64<39>(a));
+  const uint64_t mj = maj3_64(a, b, c);
+  d += t1;
+  h = t1 + S0 + mj;  // the new a
 }
 
 // SHA-512 of a message of 2 np bytes (np <= 16): the private integers as
 // int16 little-endian.  One 1024-bit block: message, the 0x80 byte, zeros,
 // the bit length in the last word.  Returns the digest words H[0..7].
+// Rounds 0..15 are unrolled (most message words are constants there); rounds
+// 16..79 run as a loop of 16 unrolled rounds that extends the schedule in
+// place, which keeps the code and the live schedule words small.
 template <int NP>
 __device__ __forceinline__ void sha512_private(const int32_t (&q)[kPixMaxPriv], uint32_t np_rt, uint64_t (&Hout)[8]) {
   const uint32_t np = NP > 0 ? (uint32_t)NP : np_rt;
@@ -100,43 +148,26 @@ __device__ __forceinline__ void sha512_private(const int32_t (&q)[kPixMaxPriv], 
   for (int i = 5; i < 15; ++i) W[i] = 0;
   W[15] = (uint64_t)(16u * np);
 
-  uint64_t a = kSha512H0[0], b = kSha512H0[1], c = kSha512H0[2], d = kSha512H0[3];
-  uint64_t e = kSha512H0[4], f = kSha512H0[5], g = kSha512H0[6], h = kSha512H0[7];
-  static_for<0, 80>([&](auto tc) {
+  uint64_t v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = kSha512H0[i];
+  static_for<0, 16>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
-    uint64_t w;
-    if constexpr (t < 16) {
-      w = W[t];
-    } else {
-      const uint64_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
+    sha512_round<t>(v, kSha512K[t] + W[t]);
+  });
+#pragma unroll 1
+  for (uint32_t base = 16; base < 80; base += 16) {
+    static_for<0, 16>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      const uint64_t w15 = W[(r + 1) & 15], w2 = W[(r + 14) & 15];
       const uint64_t s0 = xor3_64(rotr64<1>(w15), rotr64<8>(w15), w15 >> 7);
       const uint64_t s1 = xor3_64(rotr64<19>(w2), rotr64<61>(w2), w2 >> 6);
-      w = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
-      W[t & 15] = w;
-    }
-    const uint64_t S1 = xor3_64(rotr64<14>(e), rotr64<18>(e), rotr64<41>(e));
-    const uint64_t ch = (e & f) ^ (~e & g);
-    const uint64_t t1 = h + S1 + ch + kSha512K[t] + w;
-    const uint64_t S0 = xor3_64(rotr64<28>(a), rotr64<34>(a), rotr64<39>(a));
-    const uint64_t mj = (a & b) ^ (a & c) ^ (b & c);
-    const uint64_t t2 = S0 + mj;
-    h = g;
-    g = f;
-    f = e;
-    e = d + t1;
-    d = c;
-    c = b;
-    b = a;
-    a = t1 + t2;
-  });
-  Hout[0] = kSha512H0[0] + a;
-  Hout[1] = kSha512H0[1] + b;
-  Hout[2] = kSha512H0[2] + c;
-  Hout[3] = kSha512H0[3] + d;
-  Hout[4] = kSha512H0[4] + e;
-  Hout[5] = kSha512H0[5] + f;
-  Hout[6] = kSha512H0[6] + g;
-  Hout[7] = kSha512H0[7] + h;
+      W[r] += s0 + W[(r + 9) & 15] + s1;
+      sha512_round<r>(v, c_sha512.k[base + r] + W[r]);
+    });
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) Hout[i] = kSha512H0[i] + v[i];
 }
 
 // Digest bytes 8y .. 8y + 7 mask row y of the block: as a little-endian row
