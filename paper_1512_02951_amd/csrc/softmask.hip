@@ -28,6 +28,7 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kStats = 65;     // E_0 .. E_63, sum x
 constexpr int kCorrStats = 5;  // sum x, sum P, sum xP, sum x^2, sum P^2
+constexpr uint64_t kTuneStatsLdsBytes = 48u * 1024u;
 
 struct SmGeom {
   uint32_t B, H, W, Bx;
@@ -263,6 +264,7 @@ struct LossArgs {
   const double *stats;     // B x 65 (closed form) or B x 5 (corr) per mode
   uint32_t B;
   double N;                // samples per image
+  double inv_n;            // 1 / N
   double lam, budget;
   int mode;                // 0: closed form from B x 65 energies; 1: from B x 5 correlation sums
   float *gcoef;            // B x 4: a, b, mean x, mean P of dL/dP, or null
@@ -270,14 +272,13 @@ struct LossArgs {
 
 struct LossShared {
   double m[64];
-  double msum, rho2;
-  double alpha[256], beta[256], r2[256];  // per image, in chunks of 256
+  double alpha[256], beta[256], dc[256];  // per image, in chunks of 256
 };
 
 // Objective at mask m_n = sigmoid(l) for the calling thread's frequency
 // n = threadIdx.x (64 threads, one wave).  Returns the loss in every thread and
 // sets dm to dL/dm_n of the correlation part (mode 0 only; zero in mode 1) and
-// gb to the budget part 2 lam (sum m - budget).  Per image b (population
+// gb to the budget part 2 lam (sum m - budget), m_out to m_n.  Per image b (population
 // moments over the N samples):
 //   rho_b = cov(P, x) / (sd x sd P),
 //   dL/dP = a_b (x - mean x) + b_b (P - mean P),
@@ -287,20 +288,27 @@ struct LossShared {
 // sum x^2 = sum_n E_n, mean P = keep_0 mean x (only the DC basis function has
 // a nonzero mean), and dL/dm_n = -sum_b (a_b dE'_bn + b_b keep_n dE'_bn) with
 // the DC term corrected for the means.
-__device__ double sm_eval(const LossArgs &a, double l, LossShared &S, double &dm, double &gb) {
+// Sum over the wave in a fixed order (a shift-down tree into lane 0, then
+// lane 0's value to every lane): the same bits in every lane and every call.
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+  return __shfl(v, 0, 64);
+}
+
+__device__ double sm_eval(const LossArgs &a, double l, LossShared &S, double &dm, double &gb, double &m_out) {
   const int n = threadIdx.x;
   const double m = 1.0 / (1.0 + exp(-l));
+  m_out = m;
   S.m[n] = m;
-  __syncthreads();
-  if (n == 0) {
-    double ms = 0.0;
-    for (int k = 0; k < 64; ++k) ms += S.m[k];
-    S.msum = ms;
-    S.rho2 = 0.0;
-  }
+  const double msum = wave_sum_fixed(m);
   __syncthreads();
   const double keep0 = 1.0 - S.m[0];
-  dm = 0.0;
+  const double keep_n = 1.0 - m;
+  double r2 = 0.0;  // this thread's images, in image order
+  // four independent partial sums over the images (image i into i % 4) keep
+  // the loop from waiting on one long chain of dependent adds
+  double dmp[4] = {0.0, 0.0, 0.0, 0.0};
   for (uint32_t b0 = 0; b0 < a.B; b0 += 256) {
     const uint32_t nb = a.B - b0 < 256 ? a.B - b0 : 256;
     for (uint32_t i = n; i < nb; i += 64) {
@@ -312,6 +320,7 @@ __device__ double sm_eval(const LossArgs &a, double l, LossShared &S, double &dm
         sxx = 0.0;
         sxp = 0.0;
         spp = 0.0;
+#pragma unroll 8
         for (int k = 0; k < 64; ++k) {
           const double keep = 1.0 - S.m[k], e = st[k];
           sxx += e;
@@ -327,16 +336,18 @@ __device__ double sm_eval(const LossArgs &a, double l, LossShared &S, double &dm
         sxx = st[3];
         spp = st[4];
       }
-      const double N = a.N;
-      const double xm = sx / N, pm = sp / N;
-      const double cov = sxp / N - xm * pm, vx = sxx / N - xm * xm, vp = spp / N - pm * pm;
+      const double N = a.N, iN = a.inv_n;
+      const double xm = sx * iN, pm = sp * iN;
+      const double cov = sxp * iN - xm * pm, vx = sxx * iN - xm * xm, vp = spp * iN - pm * pm;
       const double sdx = sqrt(vx > 0 ? vx : 0.0), sdp = sqrt(vp > 1e-300 ? vp : 1e-300);
       const double rho = cov / (sdx * sdp + 1e-300);
       const double alpha = 2.0 * rho / ((double)a.B * N * sdx * sdp + 1e-300);
       const double beta = -2.0 * rho * rho / ((double)a.B * N * vp + 1e-300);
       S.alpha[i] = alpha;
       S.beta[i] = beta;
-      S.r2[i] = rho * rho;
+      // the DC term's correction for the means, once per image
+      S.dc[i] = alpha * N * xm * xm + beta * N * pm * xm;
+      r2 += rho * rho;
       if (a.gcoef) {
         a.gcoef[4 * b + 0] = (float)alpha;
         a.gcoef[4 * b + 1] = (float)beta;
@@ -345,27 +356,22 @@ __device__ double sm_eval(const LossArgs &a, double l, LossShared &S, double &dm
       }
     }
     __syncthreads();
-    if (n == 0)
-      for (uint32_t i = 0; i < nb; ++i) S.rho2 += S.r2[i];  // image order: deterministic
     if (a.mode == 0) {
+#pragma unroll 4
       for (uint32_t i = 0; i < nb; ++i) {
-        const double *st = a.stats + (size_t)(b0 + i) * kStats;
-        const double E = st[n], sx = st[64], N = a.N;
-        double t = S.alpha[i] * E + S.beta[i] * (1.0 - S.m[n]) * E;
-        if (n == 0) {
-          const double xm = sx / N, pm = keep0 * xm;
-          t -= S.alpha[i] * N * xm * xm + S.beta[i] * N * pm * xm;
-        }
-        dm -= t;
+        const double E = a.stats[(size_t)(b0 + i) * kStats + n];
+        double t = S.alpha[i] * E + S.beta[i] * keep_n * E;
+        if (n == 0) t -= S.dc[i];
+        dmp[i & 3] -= t;
       }
     }
     __syncthreads();
   }
-  const double over = S.msum - a.budget;
+  dm = (dmp[0] + dmp[1]) + (dmp[2] + dmp[3]);
+  const double rho2 = wave_sum_fixed(r2);
+  const double over = msum - a.budget;
   gb = 2.0 * a.lam * over;
-  const double loss = S.rho2 / (double)a.B + a.lam * over * over;
-  __syncthreads();  // S is reused by the caller's next evaluation
-  return loss;
+  return rho2 / (double)a.B + a.lam * over * over;
 }
 
 // One evaluation: loss, closed-form gradient (mode 0), budget gradient and
@@ -374,10 +380,10 @@ __global__ __launch_bounds__(64) void sm_loss_kernel(LossArgs a, const float *lo
                                                      float *grad_budget) {
   __shared__ LossShared S;
   const int n = threadIdx.x;
-  double dm, gb;
+  double dm, gb, m;
   const double l = (double)logits[n];
-  const double L = sm_eval(a, l, S, dm, gb);
-  const double m = 1.0 / (1.0 + exp(-l)), sig = m * (1.0 - m);
+  const double L = sm_eval(a, l, S, dm, gb, m);
+  const double sig = m * (1.0 - m);
   if (grad_logits) grad_logits[n] = (float)(sig * (dm + gb));
   if (grad_budget) grad_budget[n] = (float)(sig * gb);
   if (n == 0) loss[0] = L;
@@ -387,17 +393,25 @@ __global__ __launch_bounds__(64) void sm_loss_kernel(LossArgs a, const float *lo
 // (beta1 0.9, beta2 0.999, eps 1e-8), loss before each step into trace, then
 // the n_private largest logits (ties to the lower frequency) hardened into a
 // private_mask: bit z set for the zigzag position z of each chosen frequency.
+// stats_lds: number of statistics doubles staged in LDS (dynamic shared
+// memory) for the whole loop, or 0 to read them from global memory each step.
 __global__ __launch_bounds__(64) void sm_tune_kernel(LossArgs a, float *logits, uint32_t steps, double lr,
-                                                     double *trace, uint64_t *mask_out, uint32_t n_private) {
+                                                     double *trace, uint64_t *mask_out, uint32_t n_private,
+                                                     uint32_t stats_lds) {
   __shared__ LossShared S;
   __shared__ double s_l[64];
+  extern __shared__ double s_stats[];
   const int n = threadIdx.x;
+  if (stats_lds) {
+    for (uint32_t i = n; i < stats_lds; i += 64) s_stats[i] = a.stats[i];
+    __syncthreads();
+    a.stats = s_stats;
+  }
   double l = (double)logits[n], mom = 0.0, vel = 0.0, p1 = 1.0, p2 = 1.0;
   for (uint32_t t = 0; t < steps; ++t) {
-    double dm, gb;
-    const double L = sm_eval(a, l, S, dm, gb);
+    double dm, gb, m;
+    const double L = sm_eval(a, l, S, dm, gb, m);
     if (trace && n == 0) trace[t] = L;
-    const double m = 1.0 / (1.0 + exp(-l));
     const double g = m * (1.0 - m) * (dm + gb);
     mom = 0.9 * mom + 0.1 * g;
     vel = 0.999 * vel + 0.001 * g * g;
@@ -551,6 +565,7 @@ static LossArgs loss_args(const double *stats, int mode, uint32_t B, uint32_t H,
   L.stats = stats;
   L.B = B;
   L.N = (double)H * (double)W;
+  L.inv_n = 1.0 / L.N;
   L.lam = lam;
   L.budget = budget;
   L.mode = mode;
@@ -574,8 +589,12 @@ int softmask_tune(const double *stats, uint32_t B, uint32_t H, uint32_t W, float
   if (n_private > 64) return fail(SF_EINVAL, "n_private must be at most 64");
   if (!(lr > 0.0f)) return fail(SF_EINVAL, "learning rate must be positive");
   const LossArgs L = loss_args(stats, 0, B, H, W, lam, budget, nullptr);
-  hipLaunchKernelGGL(sm_tune_kernel, dim3(1), dim3(64), 0, stream, L, logits, steps, (double)lr, trace, mask,
-                     n_private);
+  // every step reads all B x 65 statistics: keep them in LDS when they fit
+  // beside the static arrays within 64 KB (B <= 94 images)
+  const uint64_t nst = (uint64_t)B * kStats;
+  const uint32_t stats_lds = nst * sizeof(double) <= kTuneStatsLdsBytes ? (uint32_t)nst : 0u;
+  hipLaunchKernelGGL(sm_tune_kernel, dim3(1), dim3(64), (size_t)stats_lds * sizeof(double), stream, L, logits, steps,
+                     (double)lr, trace, mask, n_private, stats_lds);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "soft-mask tune launch");
 }

@@ -457,10 +457,29 @@ __global__ __launch_bounds__(kFinThreads) void stats_rows_kernel(FinArgs a) {
   }
 }
 
+// Four sums over the block's threads in one fixed LDS tree (deterministic).
+__device__ void block_sum4(double (&v)[4], double (*sh)[kFinThreads]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sh[q][t] = v[q];
+  __syncthreads();
+  for (int s = kFinThreads / 2; s > 0; s >>= 1) {
+    if (t < s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh[q][t] += sh[q][t + s];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = sh[q][0];
+}
+
+// One thread per bin for the histogram sums; the scalar results are then
+// spread over threads: 0 entropies, 0-5 one (image, direction) pair
+// correlation each, 6 the image-pair figures, 7 the block-entropy summaries.
 __global__ __launch_bounds__(kFinThreads) void stats_finalize_kernel(FinArgs a) {
   __shared__ uint64_t s_m[kIntMoments];
   __shared__ double s_f[kFltMoments];
-  __shared__ double s_red[kFinThreads];
+  __shared__ double s_red[4][kFinThreads];
   const int t = threadIdx.x;
   const StatsGeom &g = a.g;
   sf_security_stats *o = a.out;
@@ -470,46 +489,60 @@ __global__ __launch_bounds__(kFinThreads) void stats_finalize_kernel(FinArgs a) 
   const uint64_t hx = rd->hx[t], hy = rd->hy[t];
   o->hist_x[t] = hx;
   o->hist_y[t] = hy;
-  const double jl = rd->rowlog[t];
-  __syncthreads();
   const uint64_t N = (uint64_t)g.C * g.H * g.W;
   const double dN = (double)N;
   const double e = dN / 256.0;
-  const double chi = block_sum(((double)hy - e) * ((double)hy - e) / e, s_red);
-  const double lx = block_sum(clog2c(hx), s_red), ly = block_sum(clog2c(hy), s_red), lxy = block_sum(jl, s_red);
+  double v[4] = {((double)hy - e) * ((double)hy - e) / e, clog2c(hx), clog2c(hy), rd->rowlog[t]};
+  block_sum4(v, s_red);  // its barriers also publish s_m and s_f
   if (t == 0) {
     o->samples = N;
     const double lN = log2(dN);
-    const double Hx = lN - lx / dN, Hy = lN - ly / dN, Hxy = lN - lxy / dN;
-    o->chi2_y = chi;
+    const double Hx = lN - v[1] / dN, Hy = lN - v[2] / dN, Hxy = lN - v[3] / dN;
+    o->chi2_y = v[0];
     o->entropy_x = Hx;
     o->entropy_y = Hy;
     o->joint_entropy = Hxy;
     o->mutual_information = Hx + Hy - Hxy;
     o->nmi = Hx * Hy > 0.0 ? (Hx + Hy - Hxy) / sqrt(Hx * Hy) : 0.0;
-    // directional pair moments from whole-plane and border sums
+  }
+  if (t < 6) {
+    // directional pair moments from whole-plane and border sums; h: x drops
+    // the last column, y the first; v: rows; d: both
+    const int im = t / 3, d = t - 3 * (t / 3);
     const uint64_t C = g.C, H = g.H, W = g.W;
-    const uint64_t n[3] = {C * H * (W - 1), C * (H - 1) * W, C * (H - 1) * (W - 1)};
-    for (int im = 0; im < 2; ++im) {
-      const uint64_t *m = s_m + im * kImgMoments;
-      uint64_t(*pm)[6] = im == 0 ? o->pair_x : o->pair_y;
-      // h: x drops the last column, y the first; v: rows; d: both
-      const uint64_t sx[3] = {m[kT1] - m[kCLS], m[kT1] - m[kRLS], m[kT1] - m[kRLS] - m[kCLS] + m[kBRS]};
-      const uint64_t sy[3] = {m[kT1] - m[kC0S], m[kT1] - m[kR0S], m[kT1] - m[kR0S] - m[kC0S] + m[kTLS]};
-      const uint64_t qx[3] = {m[kT2] - m[kCLQ], m[kT2] - m[kRLQ], m[kT2] - m[kRLQ] - m[kCLQ] + m[kBRQ]};
-      const uint64_t qy[3] = {m[kT2] - m[kC0Q], m[kT2] - m[kR0Q], m[kT2] - m[kR0Q] - m[kC0Q] + m[kTLQ]};
-      const uint64_t pr[3] = {m[kSh], m[kSv], m[kSd]};
-      double *corr = im == 0 ? o->corr_x : o->corr_y;
-      for (int d = 0; d < 3; ++d) {
-        pm[d][0] = n[d];
-        pm[d][1] = sx[d];
-        pm[d][2] = sy[d];
-        pm[d][3] = qx[d];
-        pm[d][4] = qy[d];
-        pm[d][5] = pr[d];
-        corr[d] = pearson(n[d], sx[d], sy[d], qx[d], qy[d], pr[d]);
-      }
+    const uint64_t *m = s_m + im * kImgMoments;
+    uint64_t n, sx, sy, qx, qy, pr;
+    if (d == 0) {
+      n = C * H * (W - 1);
+      sx = m[kT1] - m[kCLS];
+      sy = m[kT1] - m[kC0S];
+      qx = m[kT2] - m[kCLQ];
+      qy = m[kT2] - m[kC0Q];
+      pr = m[kSh];
+    } else if (d == 1) {
+      n = C * (H - 1) * W;
+      sx = m[kT1] - m[kRLS];
+      sy = m[kT1] - m[kR0S];
+      qx = m[kT2] - m[kRLQ];
+      qy = m[kT2] - m[kR0Q];
+      pr = m[kSv];
+    } else {
+      n = C * (H - 1) * (W - 1);
+      sx = m[kT1] - m[kRLS] - m[kCLS] + m[kBRS];
+      sy = m[kT1] - m[kR0S] - m[kC0S] + m[kTLS];
+      qx = m[kT2] - m[kRLQ] - m[kCLQ] + m[kBRQ];
+      qy = m[kT2] - m[kR0Q] - m[kC0Q] + m[kTLQ];
+      pr = m[kSd];
     }
+    uint64_t *pm = (im == 0 ? o->pair_x : o->pair_y)[d];
+    pm[0] = n;
+    pm[1] = sx;
+    pm[2] = sy;
+    pm[3] = qx;
+    pm[4] = qy;
+    pm[5] = pr;
+    (im == 0 ? o->corr_x : o->corr_y)[d] = pearson(n, sx, sy, qx, qy, pr);
+  } else if (t == 6) {
     const uint64_t sx = s_m[kT1], sy = s_m[kImgMoments + kT1];
     const uint64_t sxx = s_m[kT2], syy = s_m[kImgMoments + kT2], sxy = s_m[kCrossXY];
     o->cross[0] = N;
@@ -523,6 +556,7 @@ __global__ __launch_bounds__(kFinThreads) void stats_finalize_kernel(FinArgs a) 
     o->dif = 100.0 * (double)s_m[kBitsDiff] / (8.0 * dN);
     const uint64_t sse = sxx + syy - 2u * sxy;  // sum (x - y)^2, exact
     o->psnr = sse == 0 ? __builtin_huge_val() : 10.0 * log10(65025.0 * dN / (double)sse);
+  } else if (t == 7) {
     const double nbk = (double)((uint64_t)g.C * g.By * g.Bx);
     for (int im = 0; im < 2; ++im) {
       double *be = im == 0 ? o->block_entropy_x : o->block_entropy_y;

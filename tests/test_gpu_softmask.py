@@ -146,6 +146,21 @@ def test_tuner_matches_oracle_adam_and_hardens_the_mask():
     assert torch.equal(out, img)
 
 
+def test_tuner_with_statistics_beyond_lds():
+    # 100 images: B x 65 statistics exceed what the tuner stages in LDS (94
+    # images), so every step reads them from global memory
+    B, H, W = 100, 8, 16
+    x = _images(B, H, W)
+    l0 = _logits(3)
+    steps, lr = 10, 0.05
+    lt, trace, mask = sm.tune(x.cuda(), _dev(l0), steps=steps, lr=lr, n_private=6)
+    lref, tref = oracle.softmask_adam(x.double().numpy(), l0.astype(np.float64), steps, lr)
+    tr = trace.cpu().numpy()
+    assert np.all(np.abs(tr - tref) <= 1e-5 * np.abs(tref))
+    assert np.abs(lt.cpu().numpy() - lref).max() <= 1e-4
+    assert mask == oracle.harden(lt.cpu().numpy(), 6)
+
+
 def test_shape_errors():
     x = torch.zeros((1, 12, 16), dtype=torch.float32, device="cuda")
     with pytest.raises(sf.SefragError) as e:
