@@ -146,10 +146,11 @@ def test_tuner_matches_oracle_adam_and_hardens_the_mask():
     assert torch.equal(out, img)
 
 
-def test_tuner_with_statistics_beyond_lds():
-    # 100 images: B x 65 statistics exceed what the tuner stages in LDS (94
-    # images), so every step reads them from global memory
-    B, H, W = 100, 8, 16
+@pytest.mark.parametrize("B", [94, 100])
+def test_tuner_at_and_beyond_the_lds_statistics_limit(B):
+    # the tuner stages B x 65 statistics in LDS up to 94 images (48 880 of
+    # 49 152 bytes); at 100 every step reads them from global memory
+    H, W = 8, 16
     x = _images(B, H, W)
     l0 = _logits(3)
     steps, lr = 10, 0.05
