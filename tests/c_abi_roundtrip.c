@@ -2,8 +2,10 @@
  * runtime API, no Python.  Round-trips one deterministic 256 x 512 RGB image
  * (smooth ramps plus a hashed noise term) through the plain form (DC + 5 AC,
  * AES-CTR, exception slots), the pixel-domain strong level and the wavelet
- * form, and compares every sample.  Prints one line per form; exits non-zero
- * on the first mismatch or error. */
+ * form, and compares every sample; then takes the security statistics of
+ * the image against its strong-level public part and compares their exact
+ * integer fields with sums taken here on the host.  Prints one line per
+ * form; exits non-zero on the first mismatch or error. */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -103,6 +105,54 @@ int main(void) {
   check(dwt_frag_image(H, W, C, d_img, d_wpub, d_wpriv, &aes, NULL), "dwt_frag_image");
   check(dwt_defrag_image(H, W, C, d_wpub, d_wpriv, &aes, d_out, NULL), "dwt_defrag_image");
   ok &= compare(d_out, img, "wavelet");
+
+  /* security statistics: image X against the strong-level public part Y */
+  {
+    const size_t wsb = sf_stats_workspace_bytes();
+    void *d_ws = dalloc(wsb);
+    sf_security_stats *d_st = (sf_security_stats *)dalloc(sizeof(sf_security_stats));
+    check(sf_security_stats_compute(d_img, d_ppub, H, W, C, d_ws, wsb, d_st, NULL, NULL), "sf_security_stats_compute");
+    sf_security_stats st;
+    uint8_t *pub = (uint8_t *)malloc(n);
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(&st, d_st, sizeof st, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(pub, d_ppub, n, hipMemcpyDeviceToHost) != hipSuccess) {
+      fprintf(stderr, "statistics: copy back failed\n");
+      exit(2);
+    }
+    uint64_t hx[256] = {0}, hy[256] = {0}, cross[6] = {n, 0, 0, 0, 0, 0}, pair[6] = {0}, bits = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const uint64_t x = img[i], y = pub[i];
+      ++hx[x];
+      ++hy[y];
+      cross[1] += x;
+      cross[2] += y;
+      cross[3] += x * x;
+      cross[4] += y * y;
+      cross[5] += x * y;
+      bits += (uint64_t)__builtin_popcount((unsigned)(x ^ y));
+    }
+    /* horizontal pairs of X: (x, right neighbour) within each row of a plane */
+    for (size_t r = 0; r < (size_t)C * H; ++r)
+      for (int x = 0; x + 1 < W; ++x) {
+        const uint64_t a = img[r * W + x], b = img[r * W + x + 1];
+        ++pair[0];
+        pair[1] += a;
+        pair[2] += b;
+        pair[3] += a * a;
+        pair[4] += b * b;
+        pair[5] += a * b;
+      }
+    size_t bad = 0;
+    bad += st.samples != n;
+    for (int v = 0; v < 256; ++v) bad += (st.hist_x[v] != hx[v]) + (st.hist_y[v] != hy[v]);
+    for (int k = 0; k < 6; ++k) bad += (st.cross[k] != cross[k]) + (st.pair_x[0][k] != pair[k]);
+    bad += st.bits_differing != bits;
+    printf("statistics: %zu of %d exact fields differ\n", bad, 1 + 512 + 12 + 1);
+    ok &= bad == 0;
+    free(pub);
+    hipFree(d_ws);
+    hipFree(d_st);
+  }
 
   /* a rejected call: height not a multiple of 8 */
   sf_desc bad = d;
