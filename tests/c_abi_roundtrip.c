@@ -1,8 +1,8 @@
 /* A plain C consumer of the library: only include/sefrag.h and the HIP
  * runtime API, no Python.  Round-trips one deterministic 256 x 512 RGB image
  * (smooth ramps plus a hashed noise term) through the plain form (DC + 5 AC,
- * AES-CTR, exception slots), the pixel-domain strong level and the wavelet
- * form, and compares every sample; then takes the security statistics of
+ * AES-CTR, exception slots), the fp16 precision form (residual plane), the
+ * pixel-domain strong level and the wavelet form, and compares every sample; then takes the security statistics of
  * the image against its strong-level public part and compares their exact
  * integer fields with sums taken here on the host.  Prints one line per
  * form; exits non-zero on the first mismatch or error. */
@@ -87,6 +87,23 @@ int main(void) {
   if (hipMemcpy(&status, d_status, 4, hipMemcpyDeviceToHost) != hipSuccess || status != 0) {
     fprintf(stderr, "device status %u\n", status);
     ok = 0;
+  }
+
+  /* precision form: fp16 public values and the int8 residual plane */
+  {
+    sf_desc dl = d;
+    dl.precision = SF_FP16;
+    size_t lpb, lqb, lrb;
+    check(sf_fragment_sizes(&dl, &lpb, &lqb, &lrb), "sf_fragment_sizes fp16");
+    void *d_lpub = dalloc(lpb);
+    uint8_t *d_lpriv = (uint8_t *)dalloc(lqb);
+    int8_t *d_res = (int8_t *)dalloc(lrb);
+    check(frag_image(&dl, d_img, d_lpub, d_lpriv, NULL, d_res, &aes, d_status, NULL), "frag_image fp16");
+    check(defrag_image(&dl, d_lpub, d_lpriv, NULL, d_res, &aes, d_out, d_status, NULL), "defrag_image fp16");
+    ok &= compare(d_out, img, "precision fp16");
+    hipFree(d_lpub);
+    hipFree(d_lpriv);
+    hipFree(d_res);
   }
 
   /* pixel-domain formats, strong level */
