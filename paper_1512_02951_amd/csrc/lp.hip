@@ -292,9 +292,10 @@ __device__ __forceinline__ LpPubFetch lp_public_fetch(const uint16_t *pub_tile, 
     if (nv == 32u && ntb == 64u) {
       if (c < 4u * npub) {
         const uint32_t r = c >> 2, part = c & 3u;
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(pub_tile + r * 64u + 32u * nt + 8u * part);
-        f.v[i] = make_uint4(__builtin_nontemporal_load(src), __builtin_nontemporal_load(src + 1),
-                            __builtin_nontemporal_load(src + 2), __builtin_nontemporal_load(src + 3));
+        // default cache policy: the two halves of a tile read the two 64-byte
+        // halves of each rank's 128-byte row, and a streaming hint would let
+        // the second half fetch the line from HBM again
+        f.v[i] = *reinterpret_cast<const uint4 *>(pub_tile + r * 64u + 32u * nt + 8u * part);
       }
     } else {
       // partial tile: chunk c covers rank c / 4, blocks 8 (c % 4) .. + 7 of this half
