@@ -377,6 +377,24 @@ def _form_pixel_stats(sf, torch, synth, dev, steps, warmup, S, C, wkey, wc, whic
         "block_entropy_y_mean": round(r["block_entropy_y"][0], 5)}
 
 
+def counter_probe(sf, torch, synth, dev):
+    """Precision-form kernels under a counter pass: one 8192^2 gray image,
+    DC + 9 AC private, generated on the host so that the profiled process
+    launches no kernels but the library's (and the calibration copy)."""
+    mask, key, c0 = sf.prefix_mask(9), synth.aes_key(3), synth.ctr0(3, 0)
+    x = synth.image(8192, 8192, 1, 3, 0).to(dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    for prec in ("fp32", "fp16", "bf16"):
+        fr = sf.frag_image(x, mask, key, c0, precision=prec, status=status)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            sf.frag_image(x, mask, key, c0, precision=prec, out=fr, status=status)
+            sf.defrag_image(fr, key, c0, out=y, status=status)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y) and int(status.item()) == 0, prec
+        print("counter probe %s: round trip exact" % prec, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +408,10 @@ def main():
                     help="comma-separated subset of the companion figures: " + ",".join(FORMS))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference kernel for HBM byte counters)")
+    ap.add_argument("--counter-probe", choices=["precision"],
+                    help="only run frag + defrag three times in FP32, fp16 and bf16 on one 8192^2 gray image "
+                         "(DC + 9 AC) generated on the host, after --calibrate-copy if given: the workload of the "
+                         "HBM counter passes over the precision-form kernels; prints one line per precision")
     ap.add_argument("--graph", action="store_true", help="replay one HIP graph per step instead of direct launches")
     ap.add_argument("--eager", action="store_true", help="direct launches (the default; kept for old command lines)")
     args = ap.parse_args()
@@ -411,6 +433,9 @@ def main():
             torch.bitwise_not(a, out=b)  # one elementwise kernel: reads and writes COPY_BYTES
         torch.cuda.synchronize()
         del a, b
+    if args.counter_probe:
+        counter_probe(sf, torch, synth, dev)
+        return
     mask = sf.prefix_mask(K_PRIV)
     key = synth.aes_key(2)
     sets = make_sets(sf, synth, torch, dev, args.sets, mask, key)
