@@ -377,10 +377,22 @@ def _form_pixel_stats(sf, torch, synth, dev, steps, warmup, S, C, wkey, wc, whic
         "block_entropy_y_mean": round(r["block_entropy_y"][0], 5)}
 
 
-def counter_probe(sf, torch, synth, dev):
-    """Precision-form kernels under a counter pass: one 8192^2 gray image,
-    DC + 9 AC private, generated on the host so that the profiled process
-    launches no kernels but the library's (and the calibration copy)."""
+def counter_probe(which, sf, torch, synth, dev):
+    """Kernels under a counter pass, on inputs generated on the host so that
+    the profiled process launches almost nothing but the library's kernels
+    (and the calibration copy).  Precision form: one 8192^2 gray image,
+    DC + 9 AC private.  Differentiation form: 64 x 1024^2 FP32 images."""
+    if which == "differentiation":
+        from paper_1512_02951_amd import softmask as sm
+        x = synth.softmask_images(64, 1024, 1024).to(dev)
+        l = torch.from_numpy(synth.logits_init().astype("float32")).to(dev)
+        G = torch.randn(x.shape, generator=torch.Generator().manual_seed(5)).to(dev)
+        for _ in range(3):
+            sm.forward(x, l)
+            sm.backward(x, G, l)
+        torch.cuda.synchronize()
+        print("counter probe differentiation: done", flush=True)
+        return
     mask, key, c0 = sf.prefix_mask(9), synth.aes_key(3), synth.ctr0(3, 0)
     x = synth.image(8192, 8192, 1, 3, 0).to(dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -408,10 +420,11 @@ def main():
                     help="comma-separated subset of the companion figures: " + ",".join(FORMS))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference kernel for HBM byte counters)")
-    ap.add_argument("--counter-probe", choices=["precision"],
-                    help="only run frag + defrag three times in FP32, fp16 and bf16 on one 8192^2 gray image "
-                         "(DC + 9 AC) generated on the host, after --calibrate-copy if given: the workload of the "
-                         "HBM counter passes over the precision-form kernels; prints one line per precision")
+    ap.add_argument("--counter-probe", choices=["precision", "differentiation"],
+                    help="instead of the benchmark, the workload of an HBM counter pass, inputs generated on the "
+                         "host, after --calibrate-copy if given: 'precision' runs frag + defrag three times in "
+                         "FP32, fp16 and bf16 on one 8192^2 gray image (DC + 9 AC); 'differentiation' runs the "
+                         "soft-mask forward with P and the adjoint backward three times each on 64 x 1024^2")
     ap.add_argument("--graph", action="store_true", help="replay one HIP graph per step instead of direct launches")
     ap.add_argument("--eager", action="store_true", help="direct launches (the default; kept for old command lines)")
     args = ap.parse_args()
@@ -434,7 +447,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.counter_probe:
-        counter_probe(sf, torch, synth, dev)
+        counter_probe(args.counter_probe, sf, torch, synth, dev)
         return
     mask = sf.prefix_mask(K_PRIV)
     key = synth.aes_key(2)
