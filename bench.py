@@ -382,6 +382,22 @@ def counter_probe(which, sf, torch, synth, dev):
     the profiled process launches almost nothing but the library's kernels
     (and the calibration copy).  Precision form: one 8192^2 gray image,
     DC + 9 AC private.  Differentiation form: 64 x 1024^2 FP32 images."""
+    if which == "batching":
+        from paper_1512_02951_amd.batch import Batch
+        specs = synth.batch_specs()[:40]
+        imgs = [synth.image(h, w, c, 4, i).to(dev) for i, (h, w, c, kk) in enumerate(specs)]
+        b = Batch(imgs, [sf.prefix_mask(kk) for (_, _, _, kk) in specs], synth.aes_key(4),
+                  [synth.ctr0(4, i) for i in range(len(specs))])
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        for _ in range(3):
+            b.frag(status=status)
+            b.defrag(status=status)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0 and all(torch.equal(x, y) for x, y in zip(imgs, b.restored))
+        print("counter probe batching: %d images, %d samples, %d algorithmic bytes per direction"
+              % (len(specs), sum(x.numel() for x in imgs), sum(_bytes_plain(h, w, c, kk + 1) for (h, w, c, kk) in specs)),
+              flush=True)
+        return
     if which == "differentiation":
         from paper_1512_02951_amd import softmask as sm
         x = synth.softmask_images(64, 1024, 1024).to(dev)
@@ -420,11 +436,13 @@ def main():
                     help="comma-separated subset of the companion figures: " + ",".join(FORMS))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference kernel for HBM byte counters)")
-    ap.add_argument("--counter-probe", choices=["precision", "differentiation"],
+    ap.add_argument("--counter-probe", choices=["precision", "differentiation", "batching"],
                     help="instead of the benchmark, the workload of an HBM counter pass, inputs generated on the "
                          "host, after --calibrate-copy if given: 'precision' runs frag + defrag three times in "
                          "FP32, fp16 and bf16 on one 8192^2 gray image (DC + 9 AC); 'differentiation' runs the "
-                         "soft-mask forward with P and the adjoint backward three times each on 64 x 1024^2")
+                         "soft-mask forward with P and the adjoint backward three times each on 64 x 1024^2; "
+                         "'batching' runs the batch frag + defrag three times on the first 40 images of the "
+                         "batching workload")
     ap.add_argument("--graph", action="store_true", help="replay one HIP graph per step instead of direct launches")
     ap.add_argument("--eager", action="store_true", help="direct launches (the default; kept for old command lines)")
     args = ap.parse_args()
