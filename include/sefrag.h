@@ -184,8 +184,8 @@ typedef struct sf_batch_item {
   uint32_t height, width, channels; /* as in sf_desc (multiples of 8)             */
   uint32_t exc_per_tile;            /* exception slots per tile (see sf_exceptions) */
   uint64_t private_mask;            /* as in sf_desc                                */
-  const uint8_t *d_pixels;          /* frag input image                             */
-  uint8_t *d_restored;              /* defrag output image                          */
+  const uint8_t *d_pixels;          /* frag input image (NULL: plan not for frag)   */
+  uint8_t *d_restored;              /* defrag output image (NULL: not for defrag)   */
   float *d_public;                  /* FP32 public fragment                         */
   uint8_t *d_private;               /* private fragment                             */
   void *d_exc;                      /* exception buffer, or NULL if not needed      */
@@ -215,14 +215,18 @@ int sf_batch_plan(const sf_batch_item *items, uint32_t n_items, const uint8_t *k
                   size_t workspace_bytes, void *stream);
 
 /* Fragment / defragment every image of the planned batch: a reset of the
- * work counter plus one persistent kernel, both on `stream`. */
+ * work counter plus one persistent kernel, both on `stream`.  Returns
+ * SF_EINVAL, launching nothing, when the plan has an item without the
+ * direction's image buffer (d_pixels for frag, d_restored for defrag). */
 int sf_frag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream);
 int sf_defrag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream);
 
 /* Autotuner: times frag + defrag of the planned batch for tiles_per_grab in
  * {1,2,4,8,16} x workgroups_per_cu in {1,2,3} (one warm pass, two timed
  * round trips each) and returns the fastest; *best_ms = its round-trip time.
- * Runs the batch many times (outputs are rewritten with identical values). */
+ * Runs the batch many times (outputs are rewritten with identical values).
+ * Needs both d_pixels and d_restored on every item (else SF_EINVAL, nothing
+ * launched). */
 int sf_batch_autotune(const void *d_workspace, sf_batch_tuning *best, float *best_ms, void *stream);
 
 /* ---------------------------------------------------------------------

@@ -246,6 +246,8 @@ struct PlanInfo {
   const void *ws = nullptr;
   uint32_t n = 0, max_npriv = 0;
   uint64_t total_tiles = 0;
+  bool all_pixels = true;    // every item has d_pixels: frag can run
+  bool all_restored = true;  // every item has d_restored: defrag can run
 };
 std::vector<PlanInfo> g_plans;  // guarded by g_plan_mu
 std::mutex g_plan_mu;
@@ -309,6 +311,7 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
   if (key) aes_expand_key(key, hd->key.rk);
   uint64_t total = 0;
   uint32_t max_npriv = 1;
+  bool all_pixels = true, all_restored = true;
   for (uint32_t i = 0; i < n; ++i) {
     const sf_batch_item &it = items[i];
     sf_desc d;
@@ -320,6 +323,8 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
     Geom g;
     if (int rc = make_geom(&d, &g)) return fail(rc, "item " + std::to_string(i) + ": " + ::sf_last_error());
     if (!it.d_pixels && !it.d_restored) return fail(SF_EINVAL, "item " + std::to_string(i) + ": no image buffer");
+    all_pixels = all_pixels && it.d_pixels;
+    all_restored = all_restored && it.d_restored;
     if (!it.d_private || (g.npub && !it.d_public))
       return fail(SF_EINVAL, "item " + std::to_string(i) + ": NULL fragment pointer");
     if (((uintptr_t)it.d_pixels | (uintptr_t)it.d_restored) & 7u || ((uintptr_t)it.d_public | (uintptr_t)it.d_private) & 15u)
@@ -358,6 +363,8 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
   p.n = n;
   p.max_npriv = max_npriv;
   p.total_tiles = total;
+  p.all_pixels = all_pixels;
+  p.all_restored = all_restored;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   for (PlanInfo &q : g_plans)
     if (q.ws == d_ws) {
@@ -373,6 +380,8 @@ int batch_run(const DeviceState &ds, const void *d_ws, int which, const sf_batch
               hipStream_t stream) {
   PlanInfo p;
   if (int rc = find_plan(d_ws, &p)) return rc;
+  if (which == 0 && !p.all_pixels) return fail(SF_EINVAL, "batch frag needs d_pixels on every item of the plan");
+  if (which == 1 && !p.all_restored) return fail(SF_EINVAL, "batch defrag needs d_restored on every item of the plan");
   return launch_batch(ds, p, which, tuning, status, stream);
 }
 
@@ -380,6 +389,8 @@ int batch_autotune(const DeviceState &ds, const void *d_ws, sf_batch_tuning *bes
                    hipStream_t stream) {
   PlanInfo p;
   if (int rc = find_plan(d_ws, &p)) return rc;
+  if (!p.all_pixels || !p.all_restored)
+    return fail(SF_EINVAL, "batch autotune runs both directions: every item needs d_pixels and d_restored");
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SF_EHIP, "hipEventCreate failed");

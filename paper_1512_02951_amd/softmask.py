@@ -170,7 +170,12 @@ def _autograd():
     import torch
 
     class SoftMaskPublic(torch.autograd.Function):
-        """P = IDCT(DCT(x) (1 - sigmoid(logits))); backward = adjoint kernel."""
+        """P = IDCT(DCT(x) (1 - sigmoid(logits))); backward = adjoint kernels.
+
+        For the logits, the hand-written adjoint kernel.  For the image, the
+        map x -> P is linear with the symmetric matrix B^T diag(1 - m) B (B
+        the orthonormal block basis), so its adjoint is the same map: the
+        forward kernel applied to the upstream gradient."""
 
         @staticmethod
         def forward(ctx, x, logits):
@@ -181,13 +186,19 @@ def _autograd():
         @staticmethod
         def backward(ctx, gP):
             x, logits = ctx.saved_tensors
-            return None, backward(x, gP.contiguous(), logits)
+            gP = gP.contiguous()
+            gx = forward(gP, logits)[0] if ctx.needs_input_grad[0] else None
+            gl = backward(x, gP, logits) if ctx.needs_input_grad[1] else None
+            return gx, gl
 
     class CorrelationLoss(torch.autograd.Function):
         """mean_b rho(P_b, x_b)^2 + lam (sum sigmoid(logits) - budget)^2."""
 
         @staticmethod
         def forward(ctx, x, P, logits, lam=LAMBDA, budget=BUDGET):
+            if x.requires_grad:
+                raise ValueError("CorrelationLoss differentiates with respect to P and the logits only; "
+                                 "pass x detached (x.detach())")
             st = corr_stats(x, P)
             loss, _, gbud, gc = loss_from_stats(st, logits, x.shape, 1, lam, budget)
             ctx.save_for_backward(x, P, gc, gbud)

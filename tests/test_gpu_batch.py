@@ -113,6 +113,36 @@ def test_batch_plan_rejects_bad_items():
         Batch([x, torch.zeros((1, 12, 16), dtype=torch.uint8, device="cuda")], [3, 3], None, [bytes(16)] * 2)
 
 
+def test_batch_run_rejects_a_direction_without_its_image_buffers():
+    # a plan whose items lack d_restored (or d_pixels) is valid for the other
+    # direction only; the missing direction and the tuner (which runs both)
+    # return SF_EINVAL from host validation, launching nothing
+    import ctypes
+    from paper_1512_02951_amd import batch as sb
+    imgs = [synth.image(16, 24, 1, 4, i, device="cuda") for i in range(2)]
+    b = Batch(imgs, [sf.prefix_mask(2)] * 2, None, [bytes(16)] * 2)
+    L = sb.lib()
+    ws = ctypes.c_void_p(b.workspace.data_ptr())
+    nbytes = L.sf_batch_workspace_bytes(2)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    best, ms = sb.SfBatchTuning(), ctypes.c_float()
+    b.items[1].d_restored = None
+    sf.check(L.sf_batch_plan(b.items, 2, None, ws, nbytes, stream))
+    assert L.sf_defrag_batch(ws, None, None, stream) == sf.SF_EINVAL
+    assert L.sf_batch_autotune(ws, ctypes.byref(best), ctypes.byref(ms), stream) == sf.SF_EINVAL
+    sf.check(L.sf_frag_batch(ws, None, None, stream))
+    b.items[1].d_restored = b.restored[1].data_ptr()
+    b.items[0].d_pixels = None
+    sf.check(L.sf_batch_plan(b.items, 2, None, ws, nbytes, stream))
+    assert L.sf_frag_batch(ws, None, None, stream) == sf.SF_EINVAL
+    assert L.sf_batch_autotune(ws, ctypes.byref(best), ctypes.byref(ms), stream) == sf.SF_EINVAL
+    sf.check(L.sf_defrag_batch(ws, None, None, stream))
+    torch.cuda.synchronize()
+    # the fragments written above restore both images
+    for i in range(2):
+        assert torch.equal(b.restored[i], imgs[i])
+
+
 def test_workload4_2000_images():
     """2000 images (sides log-uniform in [256, 4096], 1 or 3 channels, k from
     {1, 2, 5, 9}, per-image nonce): every round trip exact on the GPU; 256

@@ -1,11 +1,23 @@
 """GPU parity of the differentiation form (soft frequency mask, hand-written
 adjoint) against the FP64 oracle, through the C ABI.
 
-Bars: public image P within 1e-5 absolute (samples in [0, 1]); per-image
-statistics within 1e-5 relative; loss within 1e-6 relative; dL/dlogits
-within 1e-4 of the oracle normwise (FP32 transforms and lane sums, FP64
-across lanes); the closed form also against central differences of itself
-(h = 1e-3); the tuner's loss trace and logits against the oracle's Adam.
+Bars: public image P within 1e-5 absolute (samples in [0, 1]); every
+frequency's energy E_n within a bound derived from the FP32 arithmetic (below)
+and the sample sums within 1e-5 relative; loss within 1e-6 relative;
+dL/dlogits within 1e-4 of the oracle normwise and every component within the
+bound its own terms give; the closed form also against central differences of
+itself (h = 1e-3); the tuner's loss trace and logits against the oracle's Adam.
+
+Energy bound.  Each coefficient comes from two passes of 8-point butterflies;
+every output is at most five roundings of partial sums bounded by half the
+L1 norm of its inputs, so |DCT_fp32(x)_n - DCT(x)_n| <= GAMMA * ||x_blk||_1
+with GAMMA = 16 u (about three times the ~5 u the passes can reach; u = 2^-24).
+Squaring and summing over blocks then gives
+  |E_gpu,n - E_n| <= sum_blk (2 |X_n| d + d^2) + (8 + T) u E_n,   d = GAMMA ||x_blk||_1,
+the last term for the FP32 sums of non-negative terms inside a wave (a 6-level
+lane tree, one square, T tiles in sequence; T <= the tiles of one image) before
+they go to FP64.  Unlike a bound scaled by the DC energy, it holds each high
+frequency to its own size.
 """
 import numpy as np
 import pytest
@@ -39,6 +51,67 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+U32 = 2.0 ** -24
+GAMMA = 16 * U32
+
+
+def _blocks(img):
+    H, W = img.shape
+    return img.reshape(H // 8, 8, W // 8, 8).transpose(0, 2, 1, 3).reshape(-1, 64)
+
+
+def _energy_terms(xr, gamma=GAMMA):
+    """Per image and frequency: the oracle energies E (B, 64) and the bound
+    on |E_gpu - E| derived in the module docstring."""
+    Bm = oracle.basis()
+    B, H, W = xr.shape
+    T = -(-(H // 8) * (W // 8) // 64)
+    E = np.empty((B, 64))
+    tol = np.empty((B, 64))
+    for i in range(B):
+        blk = _blocks(xr[i])
+        X = blk @ Bm.T
+        d = gamma * np.abs(blk).sum(1)
+        E[i] = (X ** 2).sum(0)
+        tol[i] = 2.0 * (np.abs(X) * d[:, None]).sum(0) + (d ** 2).sum() + (8 + T) * U32 * E[i]
+    return E, tol
+
+
+def _assert_energies(got, xr):
+    E, tol = _energy_terms(xr)
+    err = np.abs(np.asarray(got, np.float64)[:, :64] - E)
+    bad = np.argwhere(err > tol)
+    assert bad.size == 0, "energy E_n outside its bound at (image, n) %s: err %s tol %s E %s" % (
+        bad[:4].tolist(), err[tuple(bad[:4].T)], tol[tuple(bad[:4].T)], E[tuple(bad[:4].T)])
+
+
+def _assert_grad_components(g, xr, l, gamma=GAMMA):
+    """Every component of dL/dlogits within the error its own terms allow:
+    dL/dm_n = -sum_b (a_b DCT(x - mean)_n + b_b DCT(P - mean)_n) . DCT(x)_n with
+    a_b = 2 rho/(B sx sP N), b_b = -2 rho^2/(B sP^2 N); each image contributes
+    (|a_b| + |b_b|) times its energy bound, the coefficients a_b, b_b and the
+    mask carry 1e-5 relative, and the budget term 1e-5 of itself."""
+    l = np.asarray(l, np.float64)
+    B, H, W = xr.shape
+    N = H * W
+    gref, _, _ = oracle.softmask_grad(xr, l)
+    P = oracle.softmask_public(xr, l)
+    E, tolE = _energy_terms(xr, gamma)
+    m = oracle.sigmoid(l)
+    dsig = m * (1.0 - m)
+    scale = np.zeros(64)
+    for i in range(B):
+        sx, sp = xr[i].std(), P[i].std()
+        rho = oracle.pearson(P[i], xr[i])
+        ab = abs(2.0 * rho / (B * sx * sp * N)) + abs(2.0 * rho * rho / (B * sp * sp * N))
+        scale += ab * (tolE[i] + 1e-5 * E[i])
+    tol = dsig * (scale + 1e-5 * 2.0 * oracle.LAMBDA * abs(m.sum() - oracle.BUDGET)) + 1e-5 * np.abs(gref)
+    err = np.abs(np.asarray(g, np.float64) - gref)
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, "dL/dl_n outside its bound at n = %s: err %s tol %s g %s" % (
+        bad[:6].tolist(), err[bad[:6]], tol[bad[:6]], gref[bad[:6]])
+
+
 def _normrel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
@@ -58,7 +131,7 @@ def test_forward_public_image_and_statistics(B, H, W):
     assert np.abs(P.cpu().double().numpy() - Pref).max() <= TOL_P
     E, sx = oracle.softmask_stats(xr)
     got = st.cpu().numpy()
-    assert np.abs(got[:, :64] - E).max() <= TOL_STATS * E.max()
+    _assert_energies(got, xr)
     assert np.allclose(got[:, 64], sx, rtol=TOL_STATS)
 
 
@@ -70,6 +143,7 @@ def test_closed_form_loss_and_gradient(B, H, W):
     gref, Lref, _ = oracle.softmask_grad(x.double().numpy(), l.astype(np.float64))
     assert abs(loss.item() - Lref) <= TOL_LOSS * abs(Lref)
     assert _normrel(grad.cpu().numpy(), gref) <= TOL_GRAD
+    _assert_grad_components(grad.cpu().numpy(), x.double().numpy(), l)
 
 
 @pytest.mark.parametrize("B,H,W", SHAPES[1:])
@@ -82,6 +156,9 @@ def test_autograd_route_matches_oracle(B, H, W):
     gref, Lref, _ = oracle.softmask_grad(x.cpu().double().numpy(), _logits(3).astype(np.float64))
     assert abs(L.item() - Lref) <= TOL_LOSS * abs(Lref)
     assert _normrel(l.grad.cpu().numpy(), gref) <= TOL_GRAD
+    # this route also transforms the stored FP32 public image and G: twice the
+    # transform error per block
+    _assert_grad_components(l.grad.cpu().numpy(), x.cpu().double().numpy(), _logits(3), 2 * GAMMA)
 
 
 def test_adjoint_kernel_for_an_arbitrary_upstream_gradient():
@@ -92,6 +169,26 @@ def test_adjoint_kernel_for_an_arbitrary_upstream_gradient():
     g = sm.backward(x.cuda(), G.cuda(), _dev(l))
     ref = oracle.softmask_adjoint(x.double().numpy(), G.double().numpy(), l.astype(np.float64))
     assert _normrel(g.cpu().numpy(), ref) <= TOL_GRAD
+
+
+def test_image_gradient_through_the_public_map():
+    # x -> P is linear and symmetric, so dL/dx = P(logits) applied to dL/dP
+    B, H, W = 2, 72, 136
+    x = _images(B, H, W).cuda().requires_grad_(True)
+    G = np.random.default_rng(11).standard_normal((B, H, W)).astype(np.float32).astype(np.float64)
+    l = _logits(5)
+    ld = _dev(l).requires_grad_(True)
+    P = sm.SoftMaskPublic.apply(x, ld)
+    (P * torch.from_numpy(G.astype(np.float32)).cuda()).sum().backward()
+    gx_ref = oracle.softmask_public(G, l.astype(np.float64))
+    # forward and inverse transform, each within GAMMA of the block's L1 norm
+    l1 = max(np.abs(_blocks(G[i])).sum(1).max() for i in range(B))
+    assert np.abs(x.grad.cpu().double().numpy() - gx_ref).max() <= 2 * GAMMA * l1
+    ref = oracle.softmask_adjoint(x.detach().cpu().double().numpy(), G, l.astype(np.float64))
+    assert _normrel(ld.grad.cpu().numpy(), ref) <= TOL_GRAD
+    # the correlation loss differentiates with respect to P and the logits only
+    with pytest.raises(ValueError):
+        sm.CorrelationLoss.apply(x, P, ld, sm.LAMBDA, sm.BUDGET)
 
 
 def test_closed_form_against_its_finite_differences():
@@ -188,7 +285,7 @@ def test_full_size_64_images_1024_squared():
     assert _normrel(lg.grad.cpu().numpy(), gref) <= TOL_GRAD
     E, sx = oracle.softmask_stats(xr)
     got = st.cpu().numpy()
-    assert np.abs(got[:, :64] - E).max() <= TOL_STATS * E.max()
+    _assert_energies(got, xr)
     assert np.allclose(got[:, 64], sx, rtol=TOL_STATS)
     for i in (0, 37, 63):
         Pref = oracle.softmask_public(xr[i:i + 1], l.astype(np.float64))

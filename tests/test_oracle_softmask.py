@@ -140,3 +140,30 @@ def test_adam_descends_and_hardens_the_top_logits():
     assert oracle.harden(ramp, 6) == 0b111111
     # ties go to the lower natural index: n = 0, 1, 2 sit at zigzag 0, 1, 5
     assert oracle.harden(np.zeros(64), 3) == 0b100011
+
+
+def test_adam_matches_torch_optim_adam_over_many_steps():
+    # The tuner's optimiser (beta1 0.9, beta2 0.999, eps 1e-8) against torch's
+    # own Adam driven by the same oracle gradients: every step's logits and
+    # loss agree, so the moment decays, bias corrections and step size are
+    # those of the published method, not only its first step (where the
+    # recurrences cancel).
+    x = _images(B=2, H=16, W=24)
+    l0 = synth.logits_init()
+    steps, lr = 30, 0.05
+    p = torch.tensor(l0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    want_trace = []
+    want_logits = []
+    for _ in range(steps):
+        g, loss, _ = oracle.softmask_grad(x, p.detach().numpy())
+        want_trace.append(loss)
+        p.grad = torch.from_numpy(g)
+        opt.step()
+        want_logits.append(p.detach().numpy().copy())
+    for t in (1, 2, 5, steps):
+        lt, trace = oracle.softmask_adam(x, l0, steps=t, lr=lr)
+        assert np.abs(lt - want_logits[t - 1]).max() <= 1e-12
+        assert np.abs(trace - np.array(want_trace[:t])).max() <= 1e-12
+    # a long run exercises the decays well past the bias-correction transient
+    assert np.abs(want_logits[-1] - l0).max() > 10 * lr
