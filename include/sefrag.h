@@ -23,7 +23,8 @@
  *   code means nothing was enqueued.
  * - The library allocates no memory per call.  On first use of a device it
  *   uploads small constant tables (AES T-tables, integer DCT basis) and keeps
- *   them until the process ends.
+ *   them until the process ends; its code object also holds, per device, the
+ *   1 MiB static scratch array of sf_softmask_forward_noalloc.
  * - Errors: SF_* codes below; sf_last_error() returns a thread-local message
  *   for the last failing call on this thread.
  * - Device-detected conditions are OR-ed into *d_status (one uint32 the caller
@@ -370,6 +371,21 @@ size_t sf_softmask_workspace_bytes(uint32_t B, uint32_t H, uint32_t W);
  * E_n = sum over blocks of DCT(x)_n^2 (n = 0..63), then sum x. */
 int sf_softmask_forward(const float *d_x, uint32_t B, uint32_t H, uint32_t W, const float *d_logits,
                         float *d_public, double *d_stats, void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* Allocation-free variant of sf_softmask_forward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight tuning loops,
+ * harnesses that forbid allocation): the same kernels and results, with the
+ * per-workgroup partial sums in a static device array of 1 MiB that the
+ * library holds on each device it runs on until the process ends.  No
+ * workspace argument; no hipMalloc/hipFree or allocating library call.
+ * Returns SF_ERANGE, launching nothing, when the batch needs more partial
+ * sums than the array holds (sf_softmask_workspace_bytes(B, H, W) > 1 MiB,
+ * about B > 2000 images); otherwise as sf_softmask_forward.  Calls on one
+ * device share its array: calls that overlap on one device (different
+ * streams, or different host threads) race and must be serialised by the
+ * caller; calls in one stream are ordered and safe. */
+int sf_softmask_forward_noalloc(const float *d_x, uint32_t B, uint32_t H, uint32_t W, const float *d_logits,
+                                float *d_public, double *d_stats, void *stream);
 
 /* Correlation statistics of an arbitrary P: d_stats (B x 5 doubles) <-
  * sum x, sum P, sum xP, sum x^2, sum P^2 per image. */

@@ -107,6 +107,14 @@ int device_state(DeviceState **out) {
       release();
       return hip_fail(e, "hipMemcpy(tables)");
     }
+    // the allocation-free soft-mask forward's scratch array, at its address
+    // on this device (the current one)
+    void *sm_scratch = nullptr;
+    if (int rc = softmask_scratch_address(&sm_scratch)) {
+      release();
+      return rc;
+    }
+    s.d_sm_scratch = sm_scratch;
     s.num_cu = prop.multiProcessorCount;
     s.max_lds_per_block = prop.sharedMemPerBlock;
     s.d_aes_t0 = d_t0;
@@ -428,6 +436,18 @@ int sf_softmask_forward(const float *d_x, uint32_t B, uint32_t H, uint32_t W, co
   if ((rc = device_state(&ds))) return rc;
   rc = softmask_forward(*ds, d_x, B, H, W, d_logits, d_public, d_stats, d_workspace, workspace_bytes,
                         (hipStream_t)stream);
+  if (rc == SF_OK) t_last_error.clear();
+  return rc;
+}
+
+int sf_softmask_forward_noalloc(const float *d_x, uint32_t B, uint32_t H, uint32_t W, const float *d_logits,
+                                float *d_public, double *d_stats, void *stream) {
+  int rc = sm_ptrs(d_x, d_stats);
+  if (rc) return rc;
+  if (!d_logits || ((uintptr_t)d_public & 15u)) return fail(SF_EINVAL, "NULL or misaligned argument");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  rc = softmask_forward_noalloc(*ds, d_x, B, H, W, d_logits, d_public, d_stats, (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }

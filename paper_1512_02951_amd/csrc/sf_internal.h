@@ -46,6 +46,7 @@ struct DeviceState {
   uint32_t *d_q2 = nullptr;
   uint32_t *d_lp = nullptr;  // kLpTables x kLpTableWords
   size_t max_lds_per_block = 65536;
+  void *d_sm_scratch = nullptr;  // this device's copy of the soft-mask scratch array
 };
 // Lazily initialise the current device; returns SF_OK or an error code.
 int device_state(DeviceState **out);
@@ -129,6 +130,13 @@ int launch_security_stats(const DeviceState &ds, const uint8_t *x, const uint8_t
 
 // Differentiation form (softmask.hip).
 size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, uint32_t W);
+// Allocation-free forward: partial sums in a static device array of
+// kSoftmaskScratchBytes (softmask_scratch_address gives the current device's
+// copy; called once per device at initialisation).
+constexpr size_t kSoftmaskScratchBytes = size_t(1) << 20;
+int softmask_scratch_address(void **ptr);
+int softmask_forward_noalloc(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W,
+                             const float *logits, float *p_out, double *stats, hipStream_t stream);
 int softmask_forward(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W, const float *logits,
                      float *p_out, double *stats, void *ws, size_t ws_bytes, hipStream_t stream);
 int softmask_corr_stats(const DeviceState &ds, const float *x, const float *p, uint32_t B, uint32_t H, uint32_t W,

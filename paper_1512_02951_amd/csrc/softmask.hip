@@ -503,6 +503,33 @@ size_t softmask_workspace_bytes(const DeviceState &ds, uint32_t B, uint32_t H, u
   return (size_t)B * g.wg_per_image * kStats * sizeof(double) + (size_t)64 * sizeof(double);
 }
 
+// Workspace of sf_softmask_forward_noalloc: one copy per device for the life
+// of the process.  Host code must not pass this name to a kernel (it is a host
+// stand-in, not a device address); it uses the address that
+// softmask_scratch_address returns for the current device.
+static __device__ __align__(256) uint8_t scratch[kSoftmaskScratchBytes];
+
+int softmask_scratch_address(void **ptr) {
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(soft-mask scratch)");
+  *ptr = p;
+  return SF_OK;
+}
+
+int softmask_forward_noalloc(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W,
+                             const float *logits, float *p_out, double *stats, hipStream_t stream) {
+  if (int rc = sm_check(B, H, W)) return rc;
+  if (!ds.d_sm_scratch) return fail(SF_EHIP, "soft-mask scratch address not initialised");
+  // the forward writes every partial slot it later reduces: nothing to clear
+  const size_t need = softmask_workspace_bytes(ds, B, H, W);
+  if (need > kSoftmaskScratchBytes)
+    return fail(SF_ERANGE, "batch too large for the allocation-free forward: needs " + std::to_string(need) +
+                               " bytes of partial sums, the static scratch holds " +
+                               std::to_string(kSoftmaskScratchBytes));
+  return softmask_forward(ds, x, B, H, W, logits, p_out, stats, ds.d_sm_scratch, kSoftmaskScratchBytes, stream);
+}
+
 int softmask_forward(const DeviceState &ds, const float *x, uint32_t B, uint32_t H, uint32_t W, const float *logits,
                      float *p_out, double *stats, void *ws, size_t ws_bytes, hipStream_t stream) {
   if (int rc = sm_check(B, H, W)) return rc;

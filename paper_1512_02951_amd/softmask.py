@@ -31,12 +31,13 @@ def _declare(L):
     L.sf_softmask_workspace_bytes.argtypes = [u32, u32, u32]
     L.sf_softmask_workspace_bytes.restype = sz
     L.sf_softmask_forward.argtypes = [P, u32, u32, u32, P, P, P, P, sz, P]
+    L.sf_softmask_forward_noalloc.argtypes = [P, u32, u32, u32, P, P, P, P]
     L.sf_softmask_corr_stats.argtypes = [P, P, u32, u32, u32, P, P, sz, P]
     L.sf_softmask_loss.argtypes = [P, i32, P, u32, u32, u32, f32, f32, P, P, P, P, P]
     L.sf_softmask_corr_grad.argtypes = [P, P, u32, u32, u32, P, P, P, P, P, P]
     L.sf_softmask_backward.argtypes = [P, P, u32, u32, u32, P, P, P, sz, P]
     L.sf_softmask_tune.argtypes = [P, u32, u32, u32, f32, f32, u32, f32, P, P, P, u32, P]
-    for n in ("sf_softmask_forward", "sf_softmask_corr_stats", "sf_softmask_loss", "sf_softmask_corr_grad",
+    for n in ("sf_softmask_forward", "sf_softmask_forward_noalloc", "sf_softmask_corr_stats", "sf_softmask_loss", "sf_softmask_corr_grad",
               "sf_softmask_backward", "sf_softmask_tune"):
         getattr(L, n).restype = i32
 
@@ -106,6 +107,18 @@ def forward(x, logits, public=True, stats=None, ws=None, stream=None):
     check(lib().sf_softmask_forward(_p(x), B, H, W, _p(logits), _p(P), _p(stats), _p(ws.buf), ws.nbytes,
                                     _stream(stream)))
     return P, stats
+
+
+def forward_noalloc(x, logits, public, stats, stream=None):
+    """As :func:`forward` into caller-given outputs (public may be None),
+    with the library's static scratch array instead of a workspace: the call
+    allocates nothing.  Calls that overlap on one device race."""
+    B, H, W = _check_images(x)
+    _logits(logits)
+    if public is not None:
+        _check_images(public)
+    check(lib().sf_softmask_forward_noalloc(_p(x), B, H, W, _p(logits), _p(public), _p(stats), _stream(stream)))
+    return public, stats
 
 
 def corr_stats(x, P, ws=None, stream=None):
