@@ -57,3 +57,42 @@ def test_committed_counters_match_the_built_kernels():
     if code is None:
         pytest.skip("library not built")
     assert code == _profile_fields()["code_sha1"]
+
+
+def test_tile_index_matches_the_oracle_layout():
+    import numpy as np
+
+    import oracle
+    for nb, P in ((64, 58), (150, 54), (7, 3)):
+        b = np.arange(nb).repeat(P)
+        j = np.tile(np.arange(P), nb)
+        got = bench._tile_index(nb, P, b, j)
+        assert np.array_equal(got, [oracle.tile_offset(nb, P, int(bb), int(jj)) for bb, jj in zip(b, j)])
+
+
+def test_accuracy_of_sampled_blocks_against_the_oracle(monkeypatch):
+    """The cpu_baseline leg's comparison: exact public values give 0; moving
+    one value of one block by d gives d / |block|_2 for that block."""
+    import numpy as np
+
+    import oracle
+    import synth
+    x = synth.image(8, 8 * 40, 1, 2, 3).numpy()
+    mask = (1 << 6) - 1
+    ref = oracle.frag(x, mask)
+    xb = oracle.blocks_of(x)
+    pub = oracle.tile_unpack(ref["public"], 40, 58)
+    monkeypatch.setattr(bench, "ACCURACY_SAMPLES", {"a": (xb, pub.copy(), mask)})
+    assert bench.oracle_accuracy()["a"]["max"] == 0.0
+    pub[5, 7] += 0.25
+    monkeypatch.setattr(bench, "ACCURACY_SAMPLES", {"a": (xb, pub, mask)})
+    r = bench.oracle_accuracy()["a"]
+    assert r["max"] == pytest.approx(0.25 / np.linalg.norm(xb[5].astype(float)), rel=1e-3)
+    assert r["median"] == 0.0
+
+
+def test_cpu_baseline_fields():
+    r = bench.cpu_baseline(budget_s=0.5)
+    assert r["kind"] == "oracle" and r["unit"] == "MP/s" and r["cores"] >= 1
+    assert r["value"] > 0 and r["frag_MP/s"] > 0 and r["defrag_MP/s"] > 0
+    assert r["single_thread"]["MP/s"] > 0 and r["cpu_model"]

@@ -34,3 +34,9 @@ def test_bench_prints_one_contract_line():
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], abs=1e-4)
     assert 0.0 < r["frac"] < 1.0
     assert r["traffic"] is None or abs(r["traffic"] / r["bytes_per_launch"] - 1.0) < 0.05
+    # the roofline rate is the dominant kernel's bytes over its time in the loop
+    t = d[r["kernel"] + "_ms"]
+    assert t == max(d["frag_ms"], d["defrag_ms"]) and t < d["ms_per_step"]
+    assert r["achieved"] == pytest.approx(r["bytes_per_launch"] / (t * 1e-3) / 1e9, rel=1e-3)
+    assert d["frag_burst_ms"] > 0 and d["defrag_burst_ms"] > 0
+    assert d["warm_ms_per_step"] > 0 and d["graph_replay_ms_per_step"] > 0
