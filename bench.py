@@ -275,7 +275,10 @@ def kernel_bursts(sf, torch, sets, mask, key, status, n):
 
 
 def _bytes_plain(H, W, C, npriv, pub_elt=4, residual=False):
-    return algorithmic_bytes(H, W, C, npriv, pub_elt) + (H * W * C if residual else 0)
+    """Bytes of one frag (or defrag) launch; residual: the reduced-precision
+    forms' 2-bit codes and per-tile exception counts."""
+    n = H * W * C
+    return algorithmic_bytes(H, W, C, npriv, pub_elt) + ((n // 4 + 2 * ((n // 64 + 63) // 64)) if residual else 0)
 
 
 FORMS = ("precision", "batching", "differentiation", "wavelet", "pixel", "statistics")

@@ -74,13 +74,13 @@ extern "C" {
 
 /* ---- bits OR-ed into *d_status by the kernels ---- */
 #define SF_STATUS_EXC_OVERFLOW 0x1u  /* more exceptions than capacity; *d_count holds the number found */
-#define SF_STATUS_RESIDUAL_RANGE 0x2u /* a residual fell outside int8 (never for valid fragments)      */
+#define SF_STATUS_RESIDUAL_RANGE 0x2u /* reserved (no longer raised: residuals beyond +-1 go to the exception slots) */
 #define SF_STATUS_PRIVATE_RANGE 0x4u  /* a private integer fell outside int16 (never for uint8 input)  */
 
 /* ---- precisions of the transform and of the public fragment ---- */
-#define SF_FP32 0u  /* plain form: FP32 vector DCT, sparse exception list        */
-#define SF_FP16 1u  /* reduced precision: fp16 MFMA DCT, dense int8 residual plane */
-#define SF_BF16 2u  /* reduced precision: bf16 MFMA DCT (hi/lo basis), residual     */
+#define SF_FP32 0u  /* plain form: FP32 vector DCT, sparse exception list                 */
+#define SF_FP16 1u  /* reduced precision: fp16 MFMA DCT, 2-bit residual codes + exceptions */
+#define SF_BF16 2u  /* reduced precision: bf16 MFMA DCT (hi/lo basis), as SF_FP16          */
 
 typedef struct sf_desc {
   uint32_t height;        /* rows per channel, multiple of 8                         */
@@ -97,18 +97,22 @@ typedef struct sf_aes_ctr {
   uint8_t ctr0[16];
 } sf_aes_ctr;
 
-/* Exceptions of the plain (SF_FP32) form: samples whose reconstruction from
- * the stored fragments would not round back to the input (the report notes
- * the DCT cannot guarantee losslessness, Sec. 6.4.3/6.8).  They are kept in
- * per-tile slots of one device buffer of sf_exception_bytes() bytes:
+/* Exceptions: in the plain (SF_FP32) form, samples whose reconstruction
+ * from the stored fragments would not round back to the input (the report
+ * notes the DCT cannot guarantee losslessness, Sec. 6.4.3/6.8); in the
+ * reduced-precision forms, samples whose residual is not -1, 0 or +1 (their
+ * residual code is 2).  They are kept in per-tile slots of one device buffer
+ * of sf_exception_bytes() bytes:
  *   uint16 count[ntiles]                        (ntiles = ceil(blocks / 64))
  *   uint16 pos[ntiles][per_tile]   = block-in-tile * 64 + 8*y + x
  *   uint8  value[ntiles][per_tile] = the sample's value
  * each part starting on a 16-byte boundary.  frag_image writes every count
  * (a count above per_tile means slots were lost: SF_STATUS_EXC_OVERFLOW);
  * defrag_image reads them.  No clearing is needed between calls.
- * Selections of DC plus at most 4 AC coefficients never produce exceptions;
- * for them the buffer is neither read nor written and may be NULL. */
+ * In the plain form, selections of DC plus at most 4 AC coefficients never
+ * produce exceptions; for them the buffer is neither read nor written and
+ * may be NULL.  The reduced-precision forms always need the buffer (on
+ * natural and synthetic images their slots stay empty). */
 typedef struct sf_exceptions {
   void *d_buf;        /* device buffer, sf_exception_bytes(desc, per_tile) bytes  */
   uint32_t per_tile;  /* slots per 64-block tile, 1 .. 4096                      */
@@ -123,12 +127,14 @@ const char *sf_last_error(void);
 
 /* Byte sizes of the fragments for a descriptor (host only, no GPU needed).
  * Any output pointer may be NULL.  residual_bytes is 0 for SF_FP32 and
- * channels*height*width for the reduced-precision forms.
+ * channels*height*width/4 (2 bits per sample) for the reduced-precision
+ * forms.
  * Returns SF_OK, SF_EINVAL or SF_ESHAPE. */
 int sf_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private_bytes, size_t *residual_bytes);
 
 /* Byte size of an exception buffer with per_tile slots per tile (host only).
- * *needed is set to 0 when the selection can never produce exceptions.
+ * *needed is set to 0 when the selection can never produce exceptions
+ * (plain form only).
  * Returns SF_OK, SF_EINVAL, SF_ESHAPE or SF_ERANGE (per_tile > 4096). */
 int sf_exception_bytes(const sf_desc *desc, uint32_t per_tile, size_t *bytes, int *needed);
 
@@ -142,10 +148,16 @@ int sf_init(void);
  *   d_pixels  : input image, C*H*W bytes.
  *   d_public  : out, public fragment (size from sf_fragment_sizes).
  *   d_private : out, private fragment, encrypted when aes != NULL.
- *   exc       : SF_FP32 only: exception slots; required (non-NULL, with a
- *               buffer) unless sf_exception_bytes reports them not needed.
- *   d_residual: SF_FP16/SF_BF16 only: out, int8 plane [C][H][W] with
- *               x - clamp(round(reconstruction)) (NULL for SF_FP32).
+ *   exc       : exception slots; required (non-NULL, with a buffer) unless
+ *               sf_exception_bytes reports them not needed.
+ *   d_residual: SF_FP16/SF_BF16 only: out, the residual codes of
+ *               r = x - clamp(round(y)), y the inverse transform of the
+ *               stored fragments: 2 bits per sample, code 0 (r = 0),
+ *               1 (r = +1), 3 (r = -1), 2 (|r| >= 2: the sample is in the
+ *               exception slots).  One 16-byte record per block (block b at
+ *               byte 16 b); sample (y, x) of the block at bit
+ *               32 (2 (x / 4) + y / 4) + 8 (x % 4) + 2 (y % 4).  NULL for
+ *               SF_FP32.
  *   aes       : key + initial counter, or NULL to leave the private integers
  *               in clear.
  *   d_status  : device word for SF_STATUS_* bits (may be NULL).
@@ -156,8 +168,9 @@ int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uin
 
 /* defrag_image -- defragmentation (Sec. 5.2, Fig. 3): decrypt the private
  * fragment, merge with the public coefficients in zigzag order, inverse DCT,
- * round half to even, clamp to [0,255], then apply the exception list
- * (SF_FP32) or add the residual plane (SF_FP16/SF_BF16).  Restores the input
+ * round half to even, clamp to [0,255], then add the residual codes
+ * (SF_FP16/SF_BF16) and put back the samples in the exception slots.
+ * Restores the input
  * of the matching frag_image call bit for bit.  Arguments mirror frag_image;
  * d_pixels is the output. */
 int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_private, const sf_exceptions *exc,

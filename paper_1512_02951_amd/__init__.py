@@ -127,9 +127,9 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def exception_bytes(H: int, W: int, C: int, mask: int, per_tile: int):
+def exception_bytes(H: int, W: int, C: int, mask: int, per_tile: int, precision="fp32"):
     """(bytes, needed) of an exception buffer; host only."""
-    d = desc(H, W, C, mask, "fp32")
+    d = desc(H, W, C, mask, precision)
     nbytes, needed = ctypes.c_size_t(), ctypes.c_int()
     check(lib().sf_exception_bytes(ctypes.byref(d), per_tile, ctypes.byref(nbytes), ctypes.byref(needed)))
     return nbytes.value, bool(needed.value)
@@ -140,16 +140,18 @@ DEFAULT_PER_TILE = 64
 
 @dataclass
 class ExceptionList:
-    """Per-tile exception slots of the plain form (one device byte buffer)."""
+    """Per-tile exception slots (one device byte buffer): samples the plain
+    form cannot restore from its fragments, and the samples whose residual
+    the reduced-precision forms cannot code in 2 bits."""
     buf: "object"
     per_tile: int
     shape: tuple
 
     @staticmethod
-    def empty(shape, mask: int, per_tile: int = DEFAULT_PER_TILE, device="cuda"):
+    def empty(shape, mask: int, per_tile: int = DEFAULT_PER_TILE, device="cuda", precision="fp32"):
         import torch
         C, H, W = shape
-        nbytes, needed = exception_bytes(H, W, C, mask, per_tile)
+        nbytes, needed = exception_bytes(H, W, C, mask, per_tile, precision)
         buf = torch.zeros(max(nbytes, 16), dtype=torch.uint8, device=device) if needed else None
         return ExceptionList(buf, per_tile, tuple(shape))
 
@@ -212,8 +214,8 @@ def frag_image(pixels, mask: int, key: bytes | None = None, ctr0: bytes | None =
         out = Fragments(
             public=torch.empty(max(pb // esz, 1), dtype=pub_dtype, device=pixels.device),
             private=torch.empty(max(qb, 16), dtype=torch.uint8, device=pixels.device),
-            exceptions=ExceptionList.empty((C, H, W), mask, device=pixels.device) if prec == "fp32" else None,
-            residual=torch.empty(rb, dtype=torch.int8, device=pixels.device) if rb else None,
+            exceptions=ExceptionList.empty((C, H, W), mask, device=pixels.device, precision=prec),
+            residual=torch.empty(rb, dtype=torch.uint8, device=pixels.device) if rb else None,
             shape=(C, H, W), mask=mask, precision=prec)
     d = desc(H, W, C, mask, prec)
     exc = out.exceptions.c() if out.exceptions is not None else None

@@ -155,7 +155,7 @@ int sf_fragment_sizes(const sf_desc *desc, size_t *public_bytes, size_t *private
   const size_t elt = g.precision == SF_FP32 ? 4 : 2;
   if (public_bytes) *public_bytes = (size_t)g.nb * g.npub * elt;
   if (private_bytes) *private_bytes = (size_t)g.nb * g.npriv * 2;
-  if (residual_bytes) *residual_bytes = g.precision == SF_FP32 ? 0 : (size_t)g.nb * 64;
+  if (residual_bytes) *residual_bytes = g.precision == SF_FP32 ? 0 : (size_t)g.nb * 16;
   t_last_error.clear();
   return SF_OK;
 }
@@ -166,7 +166,7 @@ int sf_exception_bytes(const sf_desc *desc, uint32_t per_tile, size_t *bytes, in
   if (rc) return rc;
   if (per_tile > kMaxExcPerTile) return fail(SF_ERANGE, "per_tile must be at most 4096");
   if (bytes) *bytes = exc_layout(g, per_tile).total;
-  if (needed) *needed = mask_needs_check(g.mask) ? 1 : 0;
+  if (needed) *needed = (g.precision != SF_FP32 || mask_needs_check(g.mask)) ? 1 : 0;
   t_last_error.clear();
   return SF_OK;
 }
@@ -182,16 +182,15 @@ static int check_call(const Geom &g, const void *pix, const void *pub, const voi
   if (!pix || !priv || (g.npub && !pub)) return fail(SF_EINVAL, "NULL fragment or image pointer");
   int rc = check_alignment(pix, pub, priv);
   if (rc) return rc;
-  if (g.precision == SF_FP32) {
-    if (mask_needs_check(g.mask)) {
-      if (!exc || !exc->d_buf) return fail(SF_EINVAL, "this selection needs an exception buffer");
-      if (exc->per_tile == 0 || exc->per_tile > kMaxExcPerTile)
-        return fail(SF_ERANGE, "exception slots per tile must be 1 .. 4096");
-      if ((uintptr_t)exc->d_buf & 15u) return fail(SF_EINVAL, "exception buffer must be 16-byte aligned");
-    }
-  } else {
-    if (!residual) return fail(SF_EINVAL, "reduced-precision forms need a residual plane");
-    if ((uintptr_t)residual & 15u) return fail(SF_EINVAL, "residual plane must be 16-byte aligned");
+  if (g.precision != SF_FP32 || mask_needs_check(g.mask)) {
+    if (!exc || !exc->d_buf) return fail(SF_EINVAL, "this selection needs an exception buffer");
+    if (exc->per_tile == 0 || exc->per_tile > kMaxExcPerTile)
+      return fail(SF_ERANGE, "exception slots per tile must be 1 .. 4096");
+    if ((uintptr_t)exc->d_buf & 15u) return fail(SF_EINVAL, "exception buffer must be 16-byte aligned");
+  }
+  if (g.precision != SF_FP32) {
+    if (!residual) return fail(SF_EINVAL, "reduced-precision forms need a residual code buffer");
+    if ((uintptr_t)residual & 15u) return fail(SF_EINVAL, "residual code buffer must be 16-byte aligned");
   }
   return SF_OK;
 }
@@ -210,7 +209,8 @@ int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uin
   if (g.precision == SF_FP32)
     rc = launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, exc, a, d_status, (hipStream_t)stream);
   else
-    rc = launch_frag_lp(*ds, g, d_pixels, d_public, d_private, d_residual, a, d_status, (hipStream_t)stream);
+    rc = launch_frag_lp(*ds, g, d_pixels, d_public, d_private, exc, (uint8_t *)d_residual, a, d_status,
+                        (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }
@@ -229,7 +229,8 @@ int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_pri
   if (g.precision == SF_FP32)
     rc = launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, exc, a, d_pixels, (hipStream_t)stream);
   else
-    rc = launch_defrag_lp(*ds, g, d_public, d_private, d_residual, a, d_pixels, d_status, (hipStream_t)stream);
+    rc = launch_defrag_lp(*ds, g, d_public, d_private, exc, (const uint8_t *)d_residual, a, d_pixels, d_status,
+                          (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
 }

@@ -88,12 +88,14 @@ int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, f
                      const sf_exceptions *exc, const AesArgs &aes, uint32_t *status, hipStream_t stream);
 int launch_defrag_fp32(const DeviceState &ds, const Geom &g, const float *pub, const uint8_t *priv,
                        const sf_exceptions *exc, const AesArgs &aes, uint8_t *pix, hipStream_t stream);
-// Reduced-precision (MFMA fp16 / bf16 + int8 residual) form (lp.hip).
+// Reduced-precision (MFMA fp16 / bf16 + 2-bit residual codes and exception
+// slots) form (lp.hip).
 int launch_frag_lp(const DeviceState &ds, const Geom &g, const uint8_t *pix, void *pub, uint8_t *priv,
-                   int8_t *residual, const AesArgs &aes, uint32_t *status, hipStream_t stream);
+                   const sf_exceptions *exc, uint8_t *residual, const AesArgs &aes, uint32_t *status,
+                   hipStream_t stream);
 int launch_defrag_lp(const DeviceState &ds, const Geom &g, const void *pub, const uint8_t *priv,
-                     const int8_t *residual, const AesArgs &aes, uint8_t *pix, uint32_t *status,
-                     hipStream_t stream);
+                     const sf_exceptions *exc, const uint8_t *residual, const AesArgs &aes, uint8_t *pix,
+                     uint32_t *status, hipStream_t stream);
 // Batched form (batch.hip).
 size_t batch_workspace_bytes(uint32_t n);
 int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, const uint8_t *key, void *d_ws,

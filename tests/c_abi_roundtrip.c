@@ -1,7 +1,7 @@
 /* A plain C consumer of the library: only include/sefrag.h and the HIP
  * runtime API, no Python.  Round-trips one deterministic 256 x 512 RGB image
  * (smooth ramps plus a hashed noise term) through the plain form (DC + 5 AC,
- * AES-CTR, exception slots), the fp16 precision form (residual plane), the
+ * AES-CTR, exception slots), the fp16 precision form (residual codes), the
  * pixel-domain strong level and the wavelet form, and compares every sample; then takes the security statistics of
  * the image against its strong-level public part and compares their exact
  * integer fields with sums taken here on the host.  Prints one line per
@@ -89,21 +89,29 @@ int main(void) {
     ok = 0;
   }
 
-  /* precision form: fp16 public values and the int8 residual plane */
+  /* precision form: fp16 public values, 2-bit residual codes, exception slots */
   {
     sf_desc dl = d;
     dl.precision = SF_FP16;
-    size_t lpb, lqb, lrb;
+    size_t lpb, lqb, lrb, leb;
+    int lneeded = 0;
     check(sf_fragment_sizes(&dl, &lpb, &lqb, &lrb), "sf_fragment_sizes fp16");
+    check(sf_exception_bytes(&dl, 16, &leb, &lneeded), "sf_exception_bytes fp16");
+    if (lrb != (size_t)H * W * C / 4 || !lneeded) {
+      fprintf(stderr, "fp16 sizes: residual %zu, exceptions needed %d\n", lrb, lneeded);
+      ok = 0;
+    }
     void *d_lpub = dalloc(lpb);
     uint8_t *d_lpriv = (uint8_t *)dalloc(lqb);
     int8_t *d_res = (int8_t *)dalloc(lrb);
-    check(frag_image(&dl, d_img, d_lpub, d_lpriv, NULL, d_res, &aes, d_status, NULL), "frag_image fp16");
-    check(defrag_image(&dl, d_lpub, d_lpriv, NULL, d_res, &aes, d_out, d_status, NULL), "defrag_image fp16");
+    sf_exceptions lexc = {dalloc(leb), 16};
+    check(frag_image(&dl, d_img, d_lpub, d_lpriv, &lexc, d_res, &aes, d_status, NULL), "frag_image fp16");
+    check(defrag_image(&dl, d_lpub, d_lpriv, &lexc, d_res, &aes, d_out, d_status, NULL), "defrag_image fp16");
     ok &= compare(d_out, img, "precision fp16");
     hipFree(d_lpub);
     hipFree(d_lpriv);
     hipFree(d_res);
+    hipFree(lexc.d_buf);
   }
 
   /* pixel-domain formats, strong level */

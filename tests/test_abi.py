@@ -41,7 +41,7 @@ def test_fragment_sizes_closed_form(H, W, C, k, prec):
     esz = 4 if prec == "fp32" else 2
     assert pb == nb * (64 - npriv) * esz
     assert qb == nb * npriv * 2
-    assert rb == (0 if prec == "fp32" else H * W * C)
+    assert rb == (0 if prec == "fp32" else H * W * C // 4)  # 2-bit residual codes
 
 
 def test_workload_byte_counts():

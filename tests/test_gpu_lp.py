@@ -1,10 +1,12 @@
 """GPU parity of the reduced-precision form (fp16 / bf16 MFMA transforms with
-an int8 residual plane) against the CPU oracle, through the C ABI.
+2-bit residual codes and exception slots) against the CPU oracle, through the
+C ABI.
 
 Bars: private integers and ciphertext bit-exact; public coefficients within
 2e-3 of the FP64 oracle, normwise per block relative to the block's pixel
 norm (the stored 16-bit values included); reconstructed pixels bit-exact
-through the residual plane; residuals within int8.
+through the residual codes and the exception slots; every code-2 sample has
+an exception holding its value, and no other sample has one.
 """
 import numpy as np
 import pytest
@@ -88,12 +90,30 @@ def _check(x, mask, prec, key=None, ctr0=None, label=""):
         l1 = np.abs(oracle.blocks_of(x).astype(np.float64)).sum(axis=1)[:, None]
         bound = 0.5 * _ulp(_round_like(pub_ref, prec), prec) * (1 + 2.0 ** -7) + TRANSFORM_ERR[prec] * l1
         assert np.all(np.abs(pub - pub_ref) <= bound), "stored value beyond rounding + transform bound"
-    r = fr.residual.cpu().numpy()
-    print("  residual nonzero fraction %.3e, max |r| %d" % (np.count_nonzero(r) / r.size, np.abs(r.astype(int)).max()),
-          flush=True)
+    codes = residual_codes(fr.residual.cpu().numpy(), x.shape)
+    ei, ev, counts = fr.exceptions.decode()
+    print("  residual nonzero fraction %.3e, escapes %d" % (np.count_nonzero(codes) / codes.size, ei.size), flush=True)
+    flat = np.ascontiguousarray(x).reshape(-1)
+    assert np.array_equal(np.sort(ei), np.flatnonzero(codes.reshape(-1) == 2)), "escape codes and slots disagree"
+    assert np.array_equal(ev, flat[ei]), "exception values differ from the samples"
+    # a code of +1 / -1 means the reconstruction rounded to x - 1 / x + 1: in range
+    assert not np.any((codes.reshape(-1) == 1) & (flat == 0)) and not np.any((codes.reshape(-1) == 3) & (flat == 255))
     assert int(status.item()) == 0, "status %d" % status.item()
     assert torch.equal(y.cpu(), torch.from_numpy(x)), "round trip differs"
     return fr, ref
+
+
+def residual_codes(raw: np.ndarray, shape) -> np.ndarray:
+    """2-bit residual codes (layout of the C ABI: one 16-byte record per
+    block, sample (y, x) at bit 32 (2 (x / 4) + y / 4) + 8 (x % 4) + 2 (y % 4))
+    as an array of the image's shape."""
+    C, H, W = shape if len(shape) == 3 else (1,) + tuple(shape)
+    nb = C * H * W // 64
+    words = raw[: 16 * nb].view("<u4").reshape(nb, 4)
+    yy, xx = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    bit = 32 * (2 * (xx // 4) + yy // 4) + 8 * (xx % 4) + 2 * (yy % 4)
+    blk = (words[:, bit // 32] >> (bit % 32)) & 3  # (nb, 8, 8)
+    return blk.reshape(C, H // 8, W // 8, 8, 8).transpose(0, 1, 3, 2, 4).reshape(C, H, W)
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -113,6 +133,40 @@ def test_lp_runtime_masks_and_clear_private(prec, mask):
     x[0, :8, :8] = 255
     x[0, 8:16, :8] = 0
     _check(x, mask, prec, None, None, "lp runtime mask")
+
+
+# An 8x8 block whose bf16 public part (DC public, zigzag positions 1-5
+# private) reconstructs about 1.7 away from some of its samples: found by a
+# search over saturated blocks maximising max |IDCT(stored) - x| with bf16
+# storage of the public coefficients, so its residual needs the exception
+# slots.
+ESCAPE_BLOCK = np.array([[255, 0, 255, 0, 255, 255, 0, 0], [0, 255, 0, 0, 0, 0, 255, 0],
+                         [255, 255, 255, 255, 255, 255, 0, 0], [255, 0, 0, 255, 255, 255, 255, 255],
+                         [255, 255, 255, 255, 0, 0, 255, 0], [255, 0, 255, 255, 0, 0, 0, 0],
+                         [0, 255, 255, 255, 255, 255, 255, 255], [255, 255, 0, 0, 0, 0, 255, 255]], np.uint8)
+
+
+def test_lp_residual_beyond_one_goes_to_the_exception_slots():
+    """bf16 with DC public on blocks that reconstruct 1.7 away: their residual
+    codes are 2 and the exception slots restore the samples; with too few
+    slots the overflow bit is raised."""
+    x = np.tile(ESCAPE_BLOCK, (3, 5))[None]  # 15 copies
+    x[0, 8:16, 16:24] = np.rot90(ESCAPE_BLOCK)
+    mask = 0b111110
+    fr, _ = _check(np.ascontiguousarray(x), mask, "bf16", synth.aes_key(3), synth.ctr0(3, 2), "escapes")
+    ei, _, counts = fr.exceptions.decode()
+    assert ei.size > 0, "no sample needed an exception"
+    # the same image with one slot per tile: overflow reported
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    small = sf.Fragments(public=torch.empty_like(fr.public), private=torch.empty_like(fr.private),
+                         exceptions=sf.ExceptionList.empty(x.shape, mask, per_tile=1, precision="bf16"),
+                         residual=torch.empty_like(fr.residual), shape=fr.shape, mask=mask, precision="bf16")
+    sf.frag_image(xd, mask, None, None, precision="bf16", out=small, status=status)
+    torch.cuda.synchronize()
+    if counts.max() > 1:
+        assert int(status.item()) & sf.SF_STATUS_EXC_OVERFLOW
+    assert small.exceptions.decode()[2].max() == counts.max()
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
