@@ -65,7 +65,8 @@ int inv_coef_z(int s, int hh, int e) { return 32 * (s / 2) + 8 * (2 * (s % 2) + 
 
 }  // namespace
 
-// Table layout: word ((mt * 4 + s) * 64 + lane) * 4 + w holds elements
+// Tables: f16 forward, f16 inverse, bf16 forward hi, bf16 forward lo, bf16
+// inverse.  Layout: word ((mt * 4 + s) * 64 + lane) * 4 + w holds elements
 // e = 2w, 2w+1 of lane `lane` for M-tile mt and K-step s, i.e. the A operand
 // of v_mfma_f32_32x32x16: row i = 32 mt + lane % 32, columns
 // k = 16 s + 8 (lane / 32) + e.  Forward tables: A[i][k] = B[n][p] for the
@@ -93,7 +94,7 @@ void build_lp_tables(const double *basis, uint32_t (*lp)[kLpTableWords]) {
             };
             put(inv ? 1 : 0, h16);
             put(inv ? 4 : 2, hb);
-            put(inv ? 5 : 3, lb);
+            if (!inv) put(3, lb);
           }
 }
 
@@ -126,6 +127,11 @@ __device__ __forceinline__ void nt_store8(void *p, uint32_t a, uint32_t b) {
   const u32x2 w = {a, b};
   __builtin_nontemporal_store(w, reinterpret_cast<u32x2 *>(p));
 }
+
+#ifndef SF_LP_AES_WIDE
+#define SF_LP_AES_WIDE 0
+#endif
+using LpAes = std::conditional_t<SF_LP_AES_WIDE != 0, AesLdsWide, AesLds>;
 
 // Tiles whose private bytes go through one AES pass together: a tile of
 // DC + 9 AC holds 80 AES blocks, so two tiles fill three passes of 64 lanes
@@ -186,11 +192,15 @@ __device__ __forceinline__ void pixels16(uint32_t w, uint32_t &lo, uint32_t &hi)
 
 // Operand tables in LDS (copied once per workgroup): per table
 // 2 x 4 x 64 lanes x 16 bytes.
-// f16: forward, inverse; bf16: forward hi, forward lo, inverse hi, inverse lo.
+// f16: forward, inverse; bf16: forward hi, forward lo, inverse.  The bf16
+// forward keeps the basis to 16 significant bits (hi + lo) so the public
+// coefficients meet their bound; the inverse only decides the residual
+// codes, and one bf16 basis keeps those within +-1 (the residual absorbs the
+// difference and both directions evaluate it identically).
 template <bool BF>
 struct LpLds {
-  static constexpr int kFwd = 0, kFwdLo = 1, kInv = BF ? 2 : 1, kInvLo = 3;
-  uint4 t[BF ? 4 : 2][2 * 4 * 64];
+  static constexpr int kFwd = 0, kFwdLo = 1, kInv = BF ? 2 : 1;
+  uint4 t[BF ? 3 : 2][2 * 4 * 64];
 };
 
 template <bool BF>
@@ -207,7 +217,6 @@ __device__ __forceinline__ void load_lp_tables(LpLds<BF> &L, const uint32_t *tab
       L.t[0][i] = src[2 * kWords4 + i];
       L.t[1][i] = src[3 * kWords4 + i];
       L.t[2][i] = src[4 * kWords4 + i];
-      L.t[3][i] = src[5 * kWords4 + i];
     } else {
       L.t[0][i] = src[0 * kWords4 + i];
       L.t[1][i] = src[1 * kWords4 + i];
@@ -332,9 +341,9 @@ struct TileGroup {
   uint32_t nb0, nb1;  // blocks in each tile
 };
 
-template <bool kEncrypt>
+template <bool kEncrypt, class AesTab>
 __device__ __forceinline__ void group_ctr(const TileGroup &G, const WaveLds &W, uint32_t pstride, uint8_t *gpriv,
-                                          uint32_t npriv, int lane, const AesLds &s_aes, const AesArgs &aes) {
+                                          uint32_t npriv, int lane, const AesTab &s_aes, const AesArgs &aes) {
   const uint32_t n0 = (2u * npriv * G.nb0 + 15u) / 16u;
   const uint32_t total = n0 + (G.n > 1 ? (2u * npriv * G.nb1 + 15u) / 16u : 0u);
   for (uint32_t a = (uint32_t)lane; a < total; a += 64u) {
@@ -399,10 +408,8 @@ __device__ __forceinline__ void lp_idct(const LpLds<BF> &L, int lane, const uint
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       acc = mfma<BF>(op(L, LpLds<BF>::kInv, mt, s, lane), chi[s], acc);
-      if constexpr (BF) {
-        acc = mfma<BF>(op(L, LpLds<BF>::kInvLo, mt, s, lane), chi[s], acc);
+      if constexpr (BF)
         if (has_lo[s]) acc = mfma<BF>(op(L, LpLds<BF>::kInv, mt, s, lane), clo[s], acc);
-      }
     }
     y[mt] = acc;
   }
@@ -494,14 +501,17 @@ __device__ __forceinline__ void stage_repack(uint8_t *stage, uint32_t npriv, uin
 // frag
 // Register budget: fp16 at 4 waves per SIMD (128 VGPRs), bf16 (hi + lo
 // operands) at 3.
+#ifndef SF_LP_FP16_WAVES_PER_EU
+#define SF_LP_FP16_WAVES_PER_EU 4
+#endif
 template <bool BF>
 constexpr int lp_waves_per_eu() {
-  return BF ? 3 : 4;
+  return BF ? 3 : SF_LP_FP16_WAVES_PER_EU;
 }
 
 template <bool BF, class MP>
 __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpArgs a) {
-  __shared__ AesLds s_aes;
+  __shared__ LpAes s_aes;
   __shared__ LpLds<BF> s_tab;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
@@ -735,7 +745,7 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
 // defrag
 template <bool BF, class MP>
 __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(LpArgs a) {
-  __shared__ AesLds s_aes;
+  __shared__ LpAes s_aes;
   __shared__ LpLds<BF> s_tab;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
@@ -877,7 +887,7 @@ int lp_grid(const DeviceState &ds, const void *kernel, int waves, size_t lds, ui
 template <bool BF>
 int lp_waves(const DeviceState &ds, size_t shared, size_t per_wave, size_t *lds_out) {
   static const int cand[] = {8, 6, 4, 2, 1};
-  const size_t fixed = sizeof(AesLds) + sizeof(LpLds<BF>);
+  const size_t fixed = sizeof(LpAes) + sizeof(LpLds<BF>);
   const size_t cu_lds = 160u * 1024u;
   for (int pass = 0; pass < 2; ++pass)
     for (int w : cand) {

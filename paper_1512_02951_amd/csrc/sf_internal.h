@@ -12,8 +12,8 @@
 namespace sf {
 
 // MFMA operand tables: f16 forward, f16 inverse, bf16 forward hi/lo, bf16
-// inverse hi/lo; each 2 M-tiles x 4 K-steps x 64 lanes x 4 words.
-constexpr int kLpTables = 6;
+// inverse; each 2 M-tiles x 4 K-steps x 64 lanes x 4 words.
+constexpr int kLpTables = 5;
 constexpr int kLpTableWords = 2 * 4 * 64 * 4;
 void build_lp_tables(const double *basis, uint32_t (*lp)[kLpTableWords]);
 
