@@ -128,11 +128,6 @@ __device__ __forceinline__ void nt_store8(void *p, uint32_t a, uint32_t b) {
   __builtin_nontemporal_store(w, reinterpret_cast<u32x2 *>(p));
 }
 
-#ifndef SF_LP_AES_WIDE
-#define SF_LP_AES_WIDE 0
-#endif
-using LpAes = std::conditional_t<SF_LP_AES_WIDE != 0, AesLdsWide, AesLds>;
-
 // Tiles whose private bytes go through one AES pass together: a tile of
 // DC + 9 AC holds 80 AES blocks, so two tiles fill three passes of 64 lanes
 // where one tile alone takes two.
@@ -341,9 +336,9 @@ struct TileGroup {
   uint32_t nb0, nb1;  // blocks in each tile
 };
 
-template <bool kEncrypt, class AesTab>
+template <bool kEncrypt>
 __device__ __forceinline__ void group_ctr(const TileGroup &G, const WaveLds &W, uint32_t pstride, uint8_t *gpriv,
-                                          uint32_t npriv, int lane, const AesTab &s_aes, const AesArgs &aes) {
+                                          uint32_t npriv, int lane, const AesLds &s_aes, const AesArgs &aes) {
   const uint32_t n0 = (2u * npriv * G.nb0 + 15u) / 16u;
   const uint32_t total = n0 + (G.n > 1 ? (2u * npriv * G.nb1 + 15u) / 16u : 0u);
   for (uint32_t a = (uint32_t)lane; a < total; a += 64u) {
@@ -501,17 +496,14 @@ __device__ __forceinline__ void stage_repack(uint8_t *stage, uint32_t npriv, uin
 // frag
 // Register budget: fp16 at 4 waves per SIMD (128 VGPRs), bf16 (hi + lo
 // operands) at 3.
-#ifndef SF_LP_FP16_WAVES_PER_EU
-#define SF_LP_FP16_WAVES_PER_EU 4
-#endif
 template <bool BF>
 constexpr int lp_waves_per_eu() {
-  return BF ? 3 : SF_LP_FP16_WAVES_PER_EU;
+  return BF ? 3 : 4;
 }
 
 template <bool BF, class MP>
 __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpArgs a) {
-  __shared__ LpAes s_aes;
+  __shared__ AesLds s_aes;
   __shared__ LpLds<BF> s_tab;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
@@ -745,7 +737,7 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
 // defrag
 template <bool BF, class MP>
 __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(LpArgs a) {
-  __shared__ LpAes s_aes;
+  __shared__ AesLds s_aes;
   __shared__ LpLds<BF> s_tab;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
@@ -887,7 +879,7 @@ int lp_grid(const DeviceState &ds, const void *kernel, int waves, size_t lds, ui
 template <bool BF>
 int lp_waves(const DeviceState &ds, size_t shared, size_t per_wave, size_t *lds_out) {
   static const int cand[] = {8, 6, 4, 2, 1};
-  const size_t fixed = sizeof(LpAes) + sizeof(LpLds<BF>);
+  const size_t fixed = sizeof(AesLds) + sizeof(LpLds<BF>);
   const size_t cu_lds = 160u * 1024u;
   for (int pass = 0; pass < 2; ++pass)
     for (int w : cand) {

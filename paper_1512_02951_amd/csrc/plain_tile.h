@@ -353,6 +353,74 @@ struct NoPrefetch {
   __device__ void operator()() const {}
 };
 
+// True for compile-time selections whose private positions all lie in the
+// 4 x 4 low-frequency corner (u, v < 4; "DC + k AC" up to k = 9).
+template <class MP>
+constexpr bool corner_selection() {
+  if constexpr (!MP::kStatic) {
+    return false;
+  } else {
+    for (int z = 0; z < MP::kNPriv; ++z)
+      if (kZigZag.nat[z] / 8 > 3 || kZigZag.nat[z] % 8 > 3) return false;
+    return true;
+  }
+}
+
+template <class MP>
+constexpr bool private_nat(int n) {
+  for (int z = 0; z < MP::kNPriv; ++z)
+    if (kZigZag.nat[z] == n) return true;
+  return false;
+}
+
+// 1-D basis value c(u) cos((2x + 1) u pi / 16) for u, x < 4 from the
+// butterfly constants; b_u(7 - x) = (-1)^u b_u(x).
+template <int U, int X>
+__device__ __forceinline__ float basis1(const DctK &K) {
+  if constexpr (U == 0) return K.s0;
+  else if constexpr (U == 1) return X == 0 ? K.c1 : X == 1 ? K.c3 : X == 2 ? K.c5 : K.c7;
+  else if constexpr (U == 2) return X == 0 ? K.a : X == 1 ? K.b : X == 2 ? -K.b : -K.a;
+  else return X == 0 ? K.c3 : X == 1 ? -K.c7 : X == 2 ? -K.c1 : -K.c5;
+}
+
+// The inverse transform of the private rounding d (natural index n = 8u + v,
+// only positions of a corner selection), sample by sample: f(p, value) for
+// p = 8y + x.  Separable, with the even/odd symmetry of the 1-D basis in
+// both directions; terms of public positions are left out at compile time.
+template <class MP, class F>
+__device__ __forceinline__ void corner_estimate(const float (&d)[64], const DctK &K, F &&f) {
+  float T[4][8];  // T[u][x] = sum_v d[8u + v] b_v(x)
+  static_for<0, 4>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    static_for<0, 4>([&](auto xc) {
+      constexpr int x = decltype(xc)::value;
+      float ev = 0.0f, od = 0.0f;
+      bool he = false, ho = false;
+      static_for<0, 4>([&](auto vc) {
+        constexpr int v = decltype(vc)::value;
+        if constexpr (private_nat<MP>(8 * u + v)) {
+          float &acc = (v & 1) ? od : ev;
+          bool &has = (v & 1) ? ho : he;
+          acc = has ? __builtin_fmaf(d[8 * u + v], basis1<v, x>(K), acc) : d[8 * u + v] * basis1<v, x>(K);
+          has = true;
+        }
+      });
+      T[u][x] = ev + od;
+      T[u][7 - x] = ev - od;
+    });
+  });
+  static_for<0, 4>([&](auto yc) {
+    constexpr int y = decltype(yc)::value;
+    static_for<0, 8>([&](auto xc) {
+      constexpr int x = decltype(xc)::value;
+      const float ev = __builtin_fmaf(T[2][x], basis1<2, y>(K), T[0][x] * basis1<0, y>(K));
+      const float od = __builtin_fmaf(T[3][x], basis1<3, y>(K), T[1][x] * basis1<1, y>(K));
+      f(std::integral_constant<int, 8 * y + x>{}, ev + od);
+      f(std::integral_constant<int, 8 * (7 - y) + x>{}, ev - od);
+    });
+  });
+}
+
 // kQ2Mfma: private AC integers from q2_mfma (at most 16 private AC
 // coefficients; q2stage and Q as set up by the kernel), else from q2_acc.
 // prefetch() (which may overwrite xs with the next tile's pixels) is called
@@ -391,6 +459,10 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
   // cert = sum over private n of (|q_n - acc_n / 2^20| + E_n) * M_n bounds how far
   // the private rounding moves any reconstructed sample (table words kQ2Cert*).
   float cert = 0.0f;
+  // for selections inside the 4 x 4 low-frequency corner: the signed private
+  // rounding d_n = q_n - acc_n / 2^20 (exact in FP32) and sum_n E_n M_n
+  float dq[64];
+  float sum_em = 0.0f;
   for_each_coef<MP>(
       mask,
       [&](auto nc, uint32_t pr) {
@@ -400,6 +472,7 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
           q = (int32_t)((S + 3u + ((S >> 3) & 1u)) >> 3);  // round half even of S / 8
           const int32_t d = 8 * q - (int32_t)S;                // 8 (q - S/8), exact
           cert += (float)(d < 0 ? -d : d) * (0.125f * 0.125f);  // M_0 = 1/8, E_0 = 0
+          dq[0] = (float)d * 0.125f;
         } else {
           const cu32_ptr row = q2 + n * kQ2RowWords;
           int32_t acc;
@@ -409,6 +482,10 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
           const int32_t d = (int32_t)((uint32_t)q << 20) - acc;  // |d| <= 2^19
           const float e = __builtin_fmaf((float)(d < 0 ? -d : d), 0x1p-20f, __uint_as_float(row[kQ2CertE]));
           cert = __builtin_fmaf(e, __uint_as_float(row[kQ2CertM]), cert);
+          if constexpr (corner_selection<MP>()) {
+            dq[n] = (float)d * 0x1p-20f;
+            sum_em = __builtin_fmaf(__uint_as_float(row[kQ2CertE]), __uint_as_float(row[kQ2CertM]), sum_em);
+          }
         }
         if (valid) *reinterpret_cast<int16_t *>(lp + 2u * (pr * nt + lane)) = (int16_t)q;
         c[n] = (float)q;
@@ -424,20 +501,35 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
   if (o.exc.check) {
     uint32_t total = 0;
     if (__ballot(valid && cert >= o.cert_thr) != 0ull) {
-      idct8x8(c, K);
-#pragma unroll
-      for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // back to pixel bytes
       // miss bits placed with v_lshl_or_b32 (shift amount inline), which the
       // optimiser would otherwise turn into selects of 64 bit constants held
       // in registers across the whole tile loop
       uint32_t bad_lo = 0, bad_hi = 0;
-      static_for<0, 64>([&](auto pc) {
-        constexpr int p = decltype(pc)::value;
-        const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
-        const uint32_t miss = r != (float)byte_of(xs, p) ? 1u : 0u;
-        uint32_t &acc = p < 32 ? bad_lo : bad_hi;
-        asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(acc) : "v"(miss), "i"(p & 31));
-      });
+      if constexpr (corner_selection<MP>()) {
+        // samples whose reconstruction may miss: the signed rounding error
+        // of the private part at the sample, sum_n d_n B_n(p), within
+        // cert_thr - sum_n E_n M_n of 1/2 (the rest of the certificate's
+        // allowance bounds everything else); these go to the exception slots
+        // whether or not they would actually round wrong
+        const float thr = o.cert_thr - sum_em;
+        corner_estimate<MP>(dq, K, [&](auto pc, float e) {
+          constexpr int p = decltype(pc)::value;
+          const uint32_t miss = __builtin_fabsf(e) >= thr ? 1u : 0u;
+          uint32_t &acc = p < 32 ? bad_lo : bad_hi;
+          asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(acc) : "v"(miss), "i"(p & 31));
+        });
+      } else {
+        idct8x8(c, K);
+#pragma unroll
+        for (int w = 0; w < 16; ++w) xs[w] ^= 0x80808080u;  // back to pixel bytes
+        static_for<0, 64>([&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(c[p]), 0.0f, 255.0f);
+          const uint32_t miss = r != (float)byte_of(xs, p) ? 1u : 0u;
+          uint32_t &acc = p < 32 ? bad_lo : bad_hi;
+          asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(acc) : "v"(miss), "i"(p & 31));
+        });
+      }
       uint64_t bad = (uint64_t)bad_lo | ((uint64_t)bad_hi << 32);
       if (!valid) bad = 0;
       uint32_t slot = wave_exclusive_scan((uint32_t)__builtin_popcountll(bad), lane, total);
@@ -523,15 +615,24 @@ __device__ __forceinline__ void defrag_tile(const TileGeom &g, const DefragIn &i
   }
   // ---- the tile's exceptions, written by the lane that stored the block
   // (same thread, later store to the same address)
+  // (entries are fetched 64 at a time, one per lane, and taken in turn from
+  // the lanes that hold them)
   if (in.exc.check) {
     const uint32_t n = in.exc.count[t];
     const uint32_t m = n < in.exc.per_tile ? n : in.exc.per_tile;
-    for (uint32_t e = 0; e < m; ++e) {
+    for (uint32_t e0 = 0; e0 < m; e0 += 64u) {
+      const uint32_t e = e0 + (uint32_t)lane;
       const size_t k = (size_t)t * in.exc.per_tile + e;
-      const uint32_t pos = in.exc.pos[k];
-      // same cache policy as the row stores it overwrites
-      if (valid && (pos >> 6) == (uint32_t)lane)
-        __builtin_nontemporal_store(in.exc.val[k], p + ((pos >> 3) & 7u) * g.W + (pos & 7u));
+      const uint32_t pos_l = e < m ? (uint32_t)in.exc.pos[k] : 0u;
+      const uint32_t val_l = e < m ? (uint32_t)in.exc.val[k] : 0u;
+      const uint32_t cnt = m - e0 < 64u ? m - e0 : 64u;
+      for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)pos_l, (int)i);
+        const uint32_t val = (uint32_t)__builtin_amdgcn_readlane((int)val_l, (int)i);
+        // same cache policy as the row stores it overwrites
+        if (valid && (pos >> 6) == (uint32_t)lane)
+          __builtin_nontemporal_store((uint8_t)val, p + ((pos >> 3) & 7u) * g.W + (pos & 7u));
+      }
     }
   }
 }

@@ -254,60 +254,6 @@ __device__ __forceinline__ void aes_encrypt(uint32_t &s0, uint32_t &s1, uint32_t
   s3 = t3 ^ rk[43];
 }
 
-// The same round table without LDS bank conflicts among the 16 lanes the
-// LDS serves together: T0 in 16 interleaved copies (entry e of copy c at
-// word 16 e + c; lane l reads copy l % 16), T1..T3 as byte rotations of T0
-// taken after the lookup.  16 KB instead of 4 KB per workgroup.
-struct AesLdsWide {
-  uint32_t t0[256 * 16];
-  uint32_t rk[44];
-};
-
-__device__ __forceinline__ void aes_load_tables(AesLdsWide &L, const uint32_t *__restrict__ T0, const AesKey &K,
-                                                int tid, int nthreads) {
-  for (int i = tid; i < 256 * 16; i += nthreads) L.t0[i] = T0[i >> 4];
-  for (int i = tid; i < 44; i += nthreads) L.rk[i] = K.rk[i];
-}
-
-__device__ __forceinline__ uint32_t rotl32(uint32_t x, int n) { return __builtin_amdgcn_alignbit(x, x, 32 - n); }
-
-__device__ __forceinline__ void aes_encrypt(uint32_t &s0, uint32_t &s1, uint32_t &s2, uint32_t &s3,
-                                            const AesLdsWide &L) {
-  const uint32_t *T = L.t0 + (threadIdx.x & 15u);
-  const uint32_t *rk = L.rk;
-  s0 ^= rk[0];
-  s1 ^= rk[1];
-  s2 ^= rk[2];
-  s3 ^= rk[3];
-  auto col = [&](uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
-    return xor3(xor3(T[16u * (a & 0xffu)], rotl32(T[16u * ((b >> 8) & 0xffu)], 8),
-                     rotl32(T[16u * ((c >> 16) & 0xffu)], 16)),
-                rotl32(T[16u * (d >> 24)], 24), k);
-  };
-#pragma unroll
-  for (int r = 1; r < 10; ++r) {
-    const uint32_t t0 = col(s0, s1, s2, s3, rk[4 * r]);
-    const uint32_t t1 = col(s1, s2, s3, s0, rk[4 * r + 1]);
-    const uint32_t t2 = col(s2, s3, s0, s1, rk[4 * r + 2]);
-    const uint32_t t3 = col(s3, s0, s1, s2, rk[4 * r + 3]);
-    s0 = t0;
-    s1 = t1;
-    s2 = t2;
-    s3 = t3;
-  }
-  // last round: the S-box value is byte 2 of every T0 entry
-  auto last = [&](uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
-    return ((T[16u * (a & 0xffu)] >> 16) & 0xffu) | ((T[16u * ((b >> 8) & 0xffu)] >> 8) & 0xff00u) |
-           (T[16u * ((c >> 16) & 0xffu)] & 0xff0000u) | ((T[16u * (d >> 24)] << 8) & 0xff000000u);
-  };
-  const uint32_t f0 = last(s0, s1, s2, s3), f1 = last(s1, s2, s3, s0), f2 = last(s2, s3, s0, s1),
-                 f3 = last(s3, s0, s1, s2);
-  s0 = f0 ^ rk[40];
-  s1 = f1 ^ rk[41];
-  s2 = f2 ^ rk[42];
-  s3 = f3 ^ rk[43];
-}
-
 // Counter block ctr0 + i (mod 2^128), big-endian; (hi, lo) are the numeric
 // halves of ctr0.  Returns the four little-endian state words.
 __device__ __forceinline__ void aes_counter(uint64_t hi, uint64_t lo, uint64_t i, uint32_t &w0, uint32_t &w1,
