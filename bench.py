@@ -314,32 +314,71 @@ def measure_forms(sf, torch, synth, dev, steps, warmup, which=None):
     return out
 
 
+# Matrix-core work of the precision-form kernels per 64-block tile, DC + 9 AC
+# private: (16-bit MFMA 32x32x16 instructions, int8 MFMA 16x16x64
+# instructions).  Both take 32768 multiply-adds x 2 = 32768 flops (ops); a
+# 32x32x16 issue keeps the matrix pipe of its SIMD busy 32 cycles, a
+# 16x16x64 int8 one 16 (the busy-cycle counter SQ_VALU_MFMA_BUSY_CYCLES of a
+# counter pass equals these sums, see profiles/forms_bench.md).
+MFMA_PER_TILE = {("fp16", "frag"): (32, 12), ("fp16", "defrag"): (16, 0),
+                 ("bf16", "frag"): (52, 12), ("bf16", "defrag"): (20, 0)}
+CLOCK_HZ = 2.4e9
+SIMDS = 1024
+
+
+def mfma_figures(prec, kernel, tiles, seconds):
+    """Achieved MFMA rates and the matrix pipes' busy fraction of one launch."""
+    n16, n8 = MFMA_PER_TILE[(prec, kernel)]
+    busy = tiles * (32 * n16 + 16 * n8) / (seconds * CLOCK_HZ * SIMDS)
+    return {"fp16_or_bf16_TFLOP/s": round(tiles * n16 * 32768 / seconds / 1e12, 2),
+            "int8_TOP/s": round(tiles * n8 * 32768 / seconds / 1e12, 2), "mfma_busy_pct": round(100 * busy, 2)}
+
+
 def _form_precision(sf, torch, synth, dev, steps, warmup, status, out):
     n_img, S, k = 16, 8192, 9
     mask, key = sf.prefix_mask(k), synth.aes_key(3)
     xs = [synth.image(S, S, 1, 3, i, device=dev) for i in range(n_img)]
     ctrs = [synth.ctr0(3, i) for i in range(n_img)]
+    tiles = S * S // 64 // 64
     prec_res = {}
     for prec in ("fp32", "fp16", "bf16"):
         frs = [sf.frag_image(x, mask, key, c, precision=prec) for x, c in zip(xs, ctrs)]
         ys = [torch.empty_like(x) for x in xs]
 
-        def rt(frs=frs, ys=ys, prec=prec):
-            for x, c, fr, y in zip(xs, ctrs, frs, ys):
+        def fr_all(frs=frs, prec=prec):
+            for x, c, fr in zip(xs, ctrs, frs):
                 sf.frag_image(x, mask, key, c, precision=prec, out=fr, status=status)
+
+        def df_all(frs=frs, ys=ys):
+            for c, fr, y in zip(ctrs, frs, ys):
                 sf.defrag_image(fr, key, c, out=y, status=status)
-        g = _Eager(rt)
-        ms = time_graphs(torch, [g], steps, warmup)
+
+        ms = time_graphs(torch, [_Eager(lambda: (fr_all(), df_all()))], steps, warmup)
+        frag_ms = time_graphs(torch, [_Eager(fr_all)], steps, warmup) / n_img
+        defrag_ms = time_graphs(torch, [_Eager(df_all)], steps, warmup) / n_img
+        torch.cuda.synchronize()
         assert int(status.item()) == 0 and all(torch.equal(x, y) for x, y in zip(xs, ys))
-        ACCURACY_SAMPLES["%s_8192x8192_k9" % prec] = sample_public(torch, xs[0], frs[0], mask, 4096, 72)
         lp = prec != "fp32"
-        nbytes = 2 * n_img * _bytes_plain(S, S, 1, k + 1, 2 if lp else 4, residual=lp)
-        prec_res[prec] = {"ms_per_step": round(ms, 4), "MP/s": round(n_img * S * S / 1e6 / (ms * 1e-3), 1),
-                          "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
-        del frs, ys, g
+        per_launch = _bytes_plain(S, S, 1, k + 1, 2 if lp else 4, residual=lp)
+        r = {"ms_per_step": round(ms, 4), "MP/s": round(n_img * S * S / 1e6 / (ms * 1e-3), 1),
+             "GB/s": round(2 * n_img * per_launch / (ms * 1e-3) / 1e9, 1),
+             "frag_us_per_image": round(1e3 * frag_ms, 2), "defrag_us_per_image": round(1e3 * defrag_ms, 2),
+             "bytes_per_launch": per_launch,
+             "frag_hbm_frac": round(per_launch / (frag_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "defrag_hbm_frac": round(per_launch / (defrag_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if lp:
+            r["mfma"] = {kern: mfma_figures(prec, kern, tiles, t * 1e-3)
+                         for kern, t in (("frag", frag_ms), ("defrag", defrag_ms))}
+        prec_res[prec] = r
+        ACCURACY_SAMPLES["%s_8192x8192_k9" % prec] = sample_public(torch, xs[0], frs[0], mask, 4096, 72)
+        del frs, ys
+    prec_res["fp16_over_fp32_round_trip"] = round(prec_res["fp16"]["ms_per_step"] / prec_res["fp32"]["ms_per_step"], 4)
+    prec_res["bf16_over_fp32_round_trip"] = round(prec_res["bf16"]["ms_per_step"] / prec_res["fp32"]["ms_per_step"], 4)
     out["precision"] = {"workload": "16 x 8192^2 gray uint8, DC+9 AC private, round trip (exact)",
                         "public_error": "per block |stored public - FP64 oracle|_2 / |block|_2 over 4096 sampled "
                                         "blocks of image 0 (bars: 2e-3 fp16/bf16, 1e-5 FP32)",
+                        "timing": "16 images per step; frag and defrag also timed alone (per image); mfma: "
+                                  "matrix-core rates and busy fraction of the 1024 SIMDs at 2.4 GHz",
                         **prec_res}
     del xs
 

@@ -208,7 +208,7 @@ typedef struct sf_batch_item {
 
 /* Launch shape of a batch run: consecutive 64-block tiles a wavefront takes
  * per grab of the work queue, and workgroups (of 4 wavefronts) per compute
- * unit (0 = as many as fit).  NULL tuning = {2, 0}. */
+ * unit (0 = as many as fit).  NULL tuning = {8, 0}. */
 typedef struct sf_batch_tuning {
   uint32_t tiles_per_grab;
   uint32_t workgroups_per_cu;

@@ -58,7 +58,7 @@ def _run(cmd, verbose):
 
 CODE_HASH = os.path.join(PKG, "kernel_code_sha1.json")
 # translation units whose machine code is fingerprinted at build time
-HASHED_UNITS = ("plain.hip",)
+HASHED_UNITS = ("plain.hip", "lp.hip")
 
 
 def _llvm_tool(name):

@@ -267,7 +267,9 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   BatchArgs a;
   a.ws = (uint8_t *)p.ws;
   a.n = p.n;
-  a.tiles_per_grab = tuning && tuning->tiles_per_grab ? tuning->tiles_per_grab : 2u;
+  // default: the grab the tuner picks on the batching workload (8 tiles;
+  // larger grabs keep the lines shared by neighbouring tiles on one wave)
+  a.tiles_per_grab = tuning && tuning->tiles_per_grab ? tuning->tiles_per_grab : 8u;
   a.lds_priv_bytes = (2u * p.max_npriv * 64u + 15u) & ~15u;
   a.status = status;
   a.aes_t0 = ds.d_aes_t0;
