@@ -698,8 +698,8 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
         }
         if (bv) {
           const uint32_t off = 16u * (uint32_t)(b0 + jb) + 8u * h;
-          __builtin_amdgcn_raw_buffer_store_b32(code[0], res, off, 0, kNonTemporal);
-          __builtin_amdgcn_raw_buffer_store_b32(code[1], res, off + 4u, 0, kNonTemporal);
+          const u32x2 cw = {code[0], code[1]};  // one 8-byte store: a half writes 512 contiguous bytes
+          __builtin_amdgcn_raw_buffer_store_b64(cw, res, off, 0, kNonTemporal);
         }
 
         // ---- this half's public values, 16 bytes per lane
@@ -781,8 +781,9 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(L
         const uint32_t roff = 16u * (uint32_t)(b0 + jb) + 8u * h;
         uint32_t code0 = 0u, code1 = 0u;
         if (bv) {
-          code0 = __builtin_amdgcn_raw_buffer_load_b32(res, roff, 0, kNonTemporal);
-          code1 = __builtin_amdgcn_raw_buffer_load_b32(res, roff + 4u, 0, kNonTemporal);
+          const u32x2 cw = __builtin_amdgcn_raw_buffer_load_b64(res, roff, 0, kNonTemporal);
+          code0 = cw.x;
+          code1 = cw.y;
         }
         // ---- operands: public values straight from the fragment (tile-
         // relative offsets: the pair's ranks are 4 apart for "DC + k AC"),
