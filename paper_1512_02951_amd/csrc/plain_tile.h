@@ -264,13 +264,26 @@ __device__ __forceinline__ int32_t q2_mfma_acc(const uint8_t *stage, uint32_t a,
   return reinterpret_cast<const int32_t *>(stage + a * kQ2AccStride)[lane];
 }
 
+// Keystream word c (state column c) of counter block ctr_first + i.
+__device__ __forceinline__ uint32_t ctr_word_quad(const AesLds &s_aes, uint64_t ctr_hi, uint64_t ctr_lo,
+                                                  uint64_t i, uint32_t c) {
+  uint32_t w0, w1, w2, w3;
+  aes_counter(ctr_hi, ctr_lo, i, w0, w1, w2, w3);
+  const uint32_t w = c == 0 ? w0 : c == 1 ? w1 : c == 2 ? w2 : w3;
+  return aes_encrypt_quad(w, c, s_aes);
+}
+
 // AES-CTR over the tile's private byte range [0, tbytes) held in LDS at lp;
 // writes the result to gp.  ctr_first = index of the tile's first AES block
-// in the fragment's counter sequence.
+// in the fragment's counter sequence.  Whole passes of 64 blocks take one
+// block per lane; a last pass of at most 16 blocks takes one block per quad
+// of lanes (aes_encrypt_quad), one 4-byte word per lane.
 __device__ __forceinline__ void tile_ctr_store(uint8_t *lp, uint8_t *gp, uint32_t tbytes, int lane, const AesLds &s_aes,
                                                uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo, uint64_t ctr_first) {
   const uint32_t nblk = (tbytes + 15u) / 16u;
-  for (uint32_t i = lane; i < nblk; i += 64) {
+  const uint32_t rem = nblk & 63u;
+  const uint32_t nrow = enc && rem != 0u && rem <= 16u ? nblk - rem : nblk;  // wave-uniform
+  for (uint32_t i = lane; i < nrow; i += 64) {
     uint4 v = *reinterpret_cast<const uint4 *>(lp + 16u * i);
     if (enc) {
       uint32_t w0, w1, w2, w3;
@@ -288,6 +301,18 @@ __device__ __forceinline__ void tile_ctr_store(uint8_t *lp, uint8_t *gp, uint32_
       for (uint32_t j = 16u * i; j < tbytes; ++j) gp[j] = lp[j];
     }
   }
+  if (nrow != nblk) {
+    const uint32_t i = nrow + ((uint32_t)lane >> 2), c = (uint32_t)lane & 3u, o = 16u * i + 4u * c;
+    uint32_t v = 0u;
+    if (i < nblk) v = *reinterpret_cast<const uint32_t *>(lp + o);
+    v ^= ctr_word_quad(s_aes, ctr_hi, ctr_lo, ctr_first + i, c);  // every lane: quad permutes
+    if (o + 4u <= tbytes) {
+      *reinterpret_cast<uint32_t *>(gp + o) = v;
+    } else if (o < tbytes) {  // final, partial word of the fragment: bytes via LDS
+      *reinterpret_cast<uint32_t *>(lp + o) = v;
+      for (uint32_t j = o; j < tbytes; ++j) gp[j] = lp[j];
+    }
+  }
 }
 
 // Inverse of tile_ctr_store: global [0, tbytes) -> decrypted bytes in LDS.
@@ -295,7 +320,9 @@ __device__ __forceinline__ void tile_ctr_load(uint8_t *lp, const uint8_t *gp, ui
                                               const AesLds &s_aes, uint32_t enc, uint64_t ctr_hi, uint64_t ctr_lo,
                                               uint64_t ctr_first) {
   const uint32_t nblk = (tbytes + 15u) / 16u;
-  for (uint32_t i = lane; i < nblk; i += 64) {
+  const uint32_t rem = nblk & 63u;
+  const uint32_t nrow = enc && rem != 0u && rem <= 16u ? nblk - rem : nblk;  // wave-uniform
+  for (uint32_t i = lane; i < nrow; i += 64) {
     uint4 v;
     if (16u * i + 16u <= tbytes) {
       v = *reinterpret_cast<const uint4 *>(gp + 16u * i);
@@ -313,6 +340,17 @@ __device__ __forceinline__ void tile_ctr_load(uint8_t *lp, const uint8_t *gp, ui
       v.w ^= w3;
     }
     *reinterpret_cast<uint4 *>(lp + 16u * i) = v;
+  }
+  if (nrow != nblk) {
+    const uint32_t i = nrow + ((uint32_t)lane >> 2), c = (uint32_t)lane & 3u, o = 16u * i + 4u * c;
+    uint32_t v = 0u;
+    if (o + 4u <= tbytes) {
+      v = *reinterpret_cast<const uint32_t *>(gp + o);
+    } else if (o < tbytes) {  // never read past the end of the fragment
+      for (uint32_t j = 0; j < 4u; ++j) v |= (o + j < tbytes ? (uint32_t)gp[o + j] : 0u) << (8u * j);
+    }
+    v ^= ctr_word_quad(s_aes, ctr_hi, ctr_lo, ctr_first + i, c);  // every lane: quad permutes
+    if (i < nblk) *reinterpret_cast<uint32_t *>(lp + o) = v;
   }
 }
 

@@ -254,6 +254,36 @@ __device__ __forceinline__ void aes_encrypt(uint32_t &s0, uint32_t &s1, uint32_t
   s3 = t3 ^ rk[43];
 }
 
+// Column c of state word s from lane (lane & ~3) + ((lane + K) & 3) of the
+// same quad (DPP quad permute; every lane of the quad must be active).
+template <int K>
+__device__ __forceinline__ uint32_t quad_next(uint32_t s) {
+  constexpr int ctrl = ((0 + K) & 3) | (((1 + K) & 3) << 2) | (((2 + K) & 3) << 4) | (((3 + K) & 3) << 6);
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, ctrl, 0xf, 0xf, false);
+}
+
+// The same encryption with one AES block per quad of lanes: lane c = lane % 4
+// of the quad holds state column c (s) and computes output column c of every
+// round, taking the bytes it needs from the other three columns by quad
+// permutes.  A wave encrypts 16 blocks with 4 table lookups per lane and
+// round, where aes_encrypt takes 16 per lane for up to 64 blocks, so it is the
+// cheaper form for a tile's last 16 or fewer blocks.  The whole wave must be
+// active.
+__device__ __forceinline__ uint32_t aes_encrypt_quad(uint32_t s, uint32_t c, const AesLds &L) {
+  const uint32_t *rk = L.rk;
+  s ^= rk[c];
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    const uint32_t n1 = quad_next<1>(s), n2 = quad_next<2>(s), n3 = quad_next<3>(s);
+    s = xor3(xor3(L.t[0][s & 0xff], L.t[1][(n1 >> 8) & 0xff], L.t[2][(n2 >> 16) & 0xff]), L.t[3][n3 >> 24],
+             rk[4 * r + c]);
+  }
+  const uint32_t n1 = quad_next<1>(s), n2 = quad_next<2>(s), n3 = quad_next<3>(s);
+  const uint32_t t = (L.t[2][s & 0xff] & 0x000000ffu) | (L.t[3][(n1 >> 8) & 0xff] & 0x0000ff00u) |
+                     (L.t[0][(n2 >> 16) & 0xff] & 0x00ff0000u) | (L.t[1][n3 >> 24] & 0xff000000u);
+  return t ^ rk[40 + c];
+}
+
 // Counter block ctr0 + i (mod 2^128), big-endian; (hi, lo) are the numeric
 // halves of ctr0.  Returns the four little-endian state words.
 __device__ __forceinline__ void aes_counter(uint64_t hi, uint64_t lo, uint64_t i, uint32_t &w0, uint32_t &w1,
