@@ -185,6 +185,61 @@ int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *
                     size_t nbytes, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Launch shapes of frag_image / defrag_image and their tuner.  The same
+ * data-parallel pass over 64-block tiles (Sec. 6.4.2: the DCT stage on the
+ * GPU; Sec. 6.5.1: a series of images processed one after another) can be
+ * launched in several shapes that give identical results; which is fastest
+ * depends on the image size, the selection and the precision.  The library
+ * keeps, per device, the shape to use for each (precision, private_mask,
+ * size class) -- size class = ceil(log2(number of 64-block tiles)) -- and
+ * falls back to the form's measured default where it has none.
+ * ------------------------------------------------------------------- */
+
+/* One launch shape.  Host struct. */
+typedef struct sf_launch_shape {
+  uint32_t waves_per_group; /* wavefronts per workgroup: 1, 2, 4, 6 or 8;
+                               0 = the form's default (plain: 2; reduced
+                               precision: the largest that lets two
+                               workgroups share a compute unit's LDS)      */
+  uint32_t resident;        /* 1: one resident generation of workgroups
+                               (as many as the device holds at once) loops
+                               over the tiles; 0: the grid gives each
+                               wavefront one tile (plain) or one pair of
+                               tiles (reduced precision)                    */
+} sf_launch_shape;
+
+/* sf_set_launch_shape -- the shape frag_image (which = 0) or defrag_image
+ * (which = 1) uses on the current device for images of desc's precision,
+ * private_mask and size class; shape = NULL forgets it (back to the
+ * default).  Host only, synchronous.  SF_EINVAL for which not in {0, 1} or
+ * waves_per_group not in {0, 1, 2, 4, 6, 8} or resident not in {0, 1};
+ * SF_ENOTSUP when that many wavefronts' LDS does not fit one workgroup on
+ * this device for desc's selection. */
+int sf_set_launch_shape(const sf_desc *desc, int which, const sf_launch_shape *shape);
+
+/* sf_get_launch_shape -- the shape that the next frag_image (which = 0) or
+ * defrag_image (which = 1) for desc would use on the current device (the
+ * stored one, else the default, resolved: waves_per_group is never 0).
+ * Host only.  Returns SF_OK, or SF_EINVAL / SF_ESHAPE for bad arguments. */
+int sf_get_launch_shape(const sf_desc *desc, int which, sf_launch_shape *out);
+
+/* sf_tune_image -- times frag_image and then defrag_image of the image in
+ * every shape that fits (waves_per_group 1, 2, 4, 6, 8 x resident 0, 1),
+ * three launches each after one untimed launch, on `stream`, and stores the
+ * fastest of each direction as with sf_set_launch_shape.  Arguments as in
+ * frag_image (d_pixels in; d_public, d_private, exc, d_residual out) plus
+ * d_restored, the output of defrag_image (must not overlap the others).
+ * Synchronous: returns when the timing is done; on return the fragments and
+ * d_restored hold a frag_image and a defrag_image in the chosen shapes.
+ * best_frag / best_defrag (may be NULL) receive the shapes; frag_ms /
+ * defrag_ms (may be NULL) their average times per launch.  The call
+ * allocates a few HIP events. */
+int sf_tune_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uint8_t *d_private,
+                  const sf_exceptions *exc, int8_t *d_residual, const sf_aes_ctr *aes, uint8_t *d_restored,
+                  uint32_t *d_status, void *stream, sf_launch_shape *best_frag, sf_launch_shape *best_defrag,
+                  float *frag_ms, float *defrag_ms);
+
+/* ---------------------------------------------------------------------
  * Batched form: many images of uneven sizes and selections (plain FP32
  * form) in one persistent kernel per direction.  Images are independent
  * pieces of data (the report's arbitrary data chunked into matrices and

@@ -37,6 +37,10 @@ class SfExceptions(ctypes.Structure):
     _fields_ = [("d_buf", ctypes.c_void_p), ("per_tile", ctypes.c_uint32)]
 
 
+class SfLaunchShape(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_uint32), ("resident", ctypes.c_uint32)]
+
+
 class SefragError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("sefrag error %d: %s" % (code, msg))
@@ -66,8 +70,14 @@ def lib():
         L.defrag_image.argtypes = [ctypes.POINTER(SfDesc), P, P, ctypes.POINTER(SfExceptions), P,
                                    ctypes.POINTER(SfAesCtr), P, P, P]
         L.encrypt_private.argtypes = [ctypes.POINTER(SfAesCtr), u64, P, P, sz, P]
+        L.sf_set_launch_shape.argtypes = [ctypes.POINTER(SfDesc), i32, ctypes.POINTER(SfLaunchShape)]
+        L.sf_get_launch_shape.argtypes = [ctypes.POINTER(SfDesc), i32, ctypes.POINTER(SfLaunchShape)]
+        L.sf_tune_image.argtypes = [ctypes.POINTER(SfDesc), P, P, P, ctypes.POINTER(SfExceptions), P,
+                                    ctypes.POINTER(SfAesCtr), P, P, P, ctypes.POINTER(SfLaunchShape),
+                                    ctypes.POINTER(SfLaunchShape), ctypes.POINTER(ctypes.c_float),
+                                    ctypes.POINTER(ctypes.c_float)]
         for name in ("sf_fragment_sizes", "sf_exception_bytes", "sf_init", "frag_image", "defrag_image",
-                     "encrypt_private"):
+                     "encrypt_private", "sf_set_launch_shape", "sf_get_launch_shape", "sf_tune_image"):
             getattr(L, name).restype = i32
         _extend(L)
         _lib = L
@@ -242,6 +252,56 @@ def defrag_image(frags: Fragments, key: bytes | None = None, ctr0: bytes | None 
                             _ptr(out), _ptr(status), _stream(stream))
     check(rc)
     return out
+
+
+WHICH = {"frag": 0, "defrag": 1}
+
+
+def set_launch_shape(shape: tuple, mask: int, which: str, waves_per_group: int | None, resident: int = 0,
+                     precision="fp32") -> None:
+    """The launch shape frag_image / defrag_image use on the current device for
+    images of this (C, H, W) size class, mask and precision; waves_per_group
+    None forgets it."""
+    C, H, W = shape
+    d = desc(H, W, C, mask, precision)
+    s = SfLaunchShape(waves_per_group, resident) if waves_per_group is not None else None
+    check(lib().sf_set_launch_shape(ctypes.byref(d), WHICH[which], ctypes.byref(s) if s is not None else None))
+
+
+def launch_shape(shape: tuple, mask: int, which: str, precision="fp32") -> tuple:
+    """(waves_per_group, resident) that the next call would use."""
+    C, H, W = shape
+    d = desc(H, W, C, mask, precision)
+    s = SfLaunchShape()
+    check(lib().sf_get_launch_shape(ctypes.byref(d), WHICH[which], ctypes.byref(s)))
+    return s.waves_per_group, s.resident
+
+
+def tune_image(pixels, mask: int, key: bytes | None = None, ctr0: bytes | None = None, precision="fp32",
+               out: Fragments | None = None, restored=None, status=None, stream=None) -> dict:
+    """Times frag_image and defrag_image of ``pixels`` in every launch shape
+    and keeps the fastest for this size class, mask and precision (sf_tune_image).
+    Returns the shapes and their times; ``out`` and ``restored`` (allocated
+    if None) hold the results of a round trip in those shapes."""
+    import torch
+    if pixels.dim() == 2:
+        pixels = pixels.unsqueeze(0)
+    C, H, W = pixels.shape
+    if out is None:
+        out = frag_image(pixels, mask, key, ctr0, precision=precision, status=status, stream=stream)
+    if restored is None:
+        restored = torch.empty_like(pixels)
+    d = desc(H, W, C, mask, out.precision)
+    exc = out.exceptions.c() if out.exceptions is not None else None
+    bf, bd = SfLaunchShape(), SfLaunchShape()
+    fm, dm = ctypes.c_float(), ctypes.c_float()
+    check(lib().sf_tune_image(ctypes.byref(d), _ptr(pixels), _ptr(out.public), _ptr(out.private),
+                              ctypes.byref(exc) if exc is not None else None, _ptr(out.residual),
+                              ctypes.byref(aes_ctr(key, ctr0)) if key is not None else None, _ptr(restored),
+                              _ptr(status), _stream(stream), ctypes.byref(bf), ctypes.byref(bd),
+                              ctypes.byref(fm), ctypes.byref(dm)))
+    return {"frag": (bf.waves_per_group, bf.resident), "defrag": (bd.waves_per_group, bd.resident),
+            "frag_ms": fm.value, "defrag_ms": dm.value, "fragments": out, "restored": restored}
 
 
 def encrypt_private(key: bytes, ctr0: bytes, data, out=None, first_block: int = 0, stream=None):

@@ -126,6 +126,37 @@ int device_state(DeviceState **out) {
   return SF_OK;
 }
 
+// Size class of an image: ceil(log2(number of tiles)).
+static uint32_t size_class(const Geom &g) {
+  uint32_t c = 0;
+  while (c < 32 && (1ull << c) < g.ntiles) ++c;
+  return c;
+}
+
+static ShapeKey shape_key(const Geom &g, int which) { return ShapeKey(g.precision, g.mask, size_class(g), which); }
+
+Shape stored_shape(DeviceState &ds, const Geom &g, int which) {
+  std::lock_guard<std::mutex> lk(ds.shape_mu);
+  auto it = ds.shapes.find(shape_key(g, which));
+  if (it != ds.shapes.end()) return it->second;
+  return Shape{0u, g.precision == SF_FP32 ? 0u : 1u};
+}
+
+// The shape a launch of (g, which) would use, resolved (waves >= 1).
+static int resolved_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
+  *out = in;
+  if (g.precision == SF_FP32) {
+    if (!out->waves) out->waves = kPlainDefaultWaves;
+    return plain_lds_bytes(g, which, out->waves) <= ds.max_lds_per_block
+               ? SF_OK
+               : fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
+  }
+  if (!out->waves) out->waves = lp_default_waves(ds, g, which);
+  if (!out->waves || lp_lds_bytes(g, which, out->waves) > ds.max_lds_per_block)
+    return fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
+  return SF_OK;
+}
+
 }  // namespace sf
 
 using namespace sf;
@@ -206,10 +237,11 @@ int frag_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uin
   if ((rc = device_state(&ds))) return rc;
   AesArgs a;
   make_aes_args(aes, &a);
+  const Shape sh = stored_shape(*ds, g, 0);
   if (g.precision == SF_FP32)
-    rc = launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, exc, a, d_status, (hipStream_t)stream);
+    rc = launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, exc, a, d_status, sh, (hipStream_t)stream);
   else
-    rc = launch_frag_lp(*ds, g, d_pixels, d_public, d_private, exc, (uint8_t *)d_residual, a, d_status,
+    rc = launch_frag_lp(*ds, g, d_pixels, d_public, d_private, exc, (uint8_t *)d_residual, a, d_status, sh,
                         (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
@@ -226,13 +258,136 @@ int defrag_image(const sf_desc *desc, const void *d_public, const uint8_t *d_pri
   if ((rc = device_state(&ds))) return rc;
   AesArgs a;
   make_aes_args(aes, &a);
+  const Shape sh = stored_shape(*ds, g, 1);
   if (g.precision == SF_FP32)
-    rc = launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, exc, a, d_pixels, (hipStream_t)stream);
+    rc = launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, exc, a, d_pixels, sh, (hipStream_t)stream);
   else
-    rc = launch_defrag_lp(*ds, g, d_public, d_private, exc, (const uint8_t *)d_residual, a, d_pixels, d_status,
+    rc = launch_defrag_lp(*ds, g, d_public, d_private, exc, (const uint8_t *)d_residual, a, d_pixels, d_status, sh,
                           (hipStream_t)stream);
   if (rc == SF_OK) t_last_error.clear();
   return rc;
+}
+
+static bool valid_shape(const sf_launch_shape *s) {
+  const uint32_t w = s->waves_per_group;
+  return (w == 0 || w == 1 || w == 2 || w == 4 || w == 6 || w == 8) && s->resident <= 1;
+}
+
+int sf_set_launch_shape(const sf_desc *desc, int which, const sf_launch_shape *shape) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  if (which != 0 && which != 1) return fail(SF_EINVAL, "which must be 0 (frag) or 1 (defrag)");
+  if (shape && !valid_shape(shape)) return fail(SF_EINVAL, "waves_per_group must be 0, 1, 2, 4, 6 or 8; resident 0 or 1");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  if (shape) {
+    Shape r;
+    if ((rc = resolved_shape(*ds, g, which, Shape{shape->waves_per_group, shape->resident}, &r))) return rc;
+    std::lock_guard<std::mutex> lk(ds->shape_mu);
+    ds->shapes[shape_key(g, which)] = Shape{shape->waves_per_group, shape->resident};
+  } else {
+    std::lock_guard<std::mutex> lk(ds->shape_mu);
+    ds->shapes.erase(shape_key(g, which));
+  }
+  t_last_error.clear();
+  return SF_OK;
+}
+
+int sf_get_launch_shape(const sf_desc *desc, int which, sf_launch_shape *out) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  if ((which != 0 && which != 1) || !out) return fail(SF_EINVAL, "which must be 0 or 1 and out non-NULL");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  Shape r;
+  if ((rc = resolved_shape(*ds, g, which, stored_shape(*ds, g, which), &r))) return rc;
+  out->waves_per_group = r.waves;
+  out->resident = r.resident;
+  t_last_error.clear();
+  return SF_OK;
+}
+
+int sf_tune_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, uint8_t *d_private,
+                  const sf_exceptions *exc, int8_t *d_residual, const sf_aes_ctr *aes, uint8_t *d_restored,
+                  uint32_t *d_status, void *stream, sf_launch_shape *best_frag, sf_launch_shape *best_defrag,
+                  float *frag_ms, float *defrag_ms) {
+  Geom g;
+  int rc = make_geom(desc, &g);
+  if (rc) return rc;
+  if ((rc = check_call(g, d_pixels, d_public, d_private, exc, d_residual))) return rc;
+  if (!d_restored || ((uintptr_t)d_restored & 7u)) return fail(SF_EINVAL, "d_restored must be an 8-byte aligned buffer");
+  DeviceState *ds;
+  if ((rc = device_state(&ds))) return rc;
+  AesArgs a;
+  make_aes_args(aes, &a);
+  hipStream_t st = (hipStream_t)stream;
+  auto run = [&](int which, const Shape &sh) {
+    if (which == 0)
+      return g.precision == SF_FP32
+                 ? launch_frag_fp32(*ds, g, d_pixels, (float *)d_public, d_private, exc, a, d_status, sh, st)
+                 : launch_frag_lp(*ds, g, d_pixels, d_public, d_private, exc, (uint8_t *)d_residual, a, d_status, sh,
+                                  st);
+    return g.precision == SF_FP32
+               ? launch_defrag_fp32(*ds, g, (const float *)d_public, d_private, exc, a, d_restored, sh, st)
+               : launch_defrag_lp(*ds, g, d_public, d_private, exc, (const uint8_t *)d_residual, a, d_restored,
+                                  d_status, sh, st);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he;
+  if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he, "hipEventCreate");
+  if ((he = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(he, "hipEventCreate");
+  }
+  static const uint32_t waves[] = {1, 2, 4, 6, 8};
+  Shape best[2] = {};
+  float best_ms[2] = {0.0f, 0.0f};
+  for (int which = 0; which < 2 && rc == SF_OK; ++which) {
+    // defrag is timed on fragments made in frag's chosen shape
+    if (which == 1 && (rc = run(0, best[0]))) break;
+    bool any = false;
+    for (uint32_t res = 0; res < 2 && rc == SF_OK; ++res)
+      for (uint32_t w : waves) {
+        Shape sh{w, res}, r;
+        if (resolved_shape(*ds, g, which, sh, &r)) continue;  // does not fit: not a candidate
+        if ((rc = run(which, sh))) break;
+        if ((he = hipEventRecord(e0, st)) != hipSuccess) { rc = hip_fail(he, "hipEventRecord"); break; }
+        for (int i = 0; i < 3 && rc == SF_OK; ++i) rc = run(which, sh);
+        if (rc) break;
+        float ms = 0.0f;
+        if ((he = hipEventRecord(e1, st)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess ||
+            (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+          rc = hip_fail(he, "timing a launch shape");
+          break;
+        }
+        ms /= 3.0f;
+        if (!any || ms < best_ms[which]) {
+          best[which] = sh;
+          best_ms[which] = ms;
+          any = true;
+        }
+      }
+    if (rc == SF_OK && !any) rc = fail(SF_ENOTSUP, "no launch shape fits this selection on this device");
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(ds->shape_mu);
+    ds->shapes[shape_key(g, 0)] = best[0];
+    ds->shapes[shape_key(g, 1)] = best[1];
+  }
+  // leave the buffers holding a frag and a defrag in the chosen shapes
+  if ((rc = run(0, best[0])) || (rc = run(1, best[1]))) return rc;
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  if (best_frag) *best_frag = sf_launch_shape{best[0].waves, best[0].resident};
+  if (best_defrag) *best_defrag = sf_launch_shape{best[1].waves, best[1].resident};
+  if (frag_ms) *frag_ms = best_ms[0];
+  if (defrag_ms) *defrag_ms = best_ms[1];
+  t_last_error.clear();
+  return SF_OK;
 }
 
 size_t sf_batch_workspace_bytes(uint32_t n_items) { return batch_workspace_bytes(n_items); }

@@ -865,69 +865,52 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(L
 
 // ---------------------------------------------------------------------------
 // launchers
-int lp_grid(const DeviceState &ds, const void *kernel, int waves, size_t lds, uint32_t ntiles) {
+// Dynamic LDS of a workgroup: `shared` (frag: the quantiser's B operands)
+// plus `per_wave` for each wavefront (private stages; frag: also the public
+// stage of one half).
+struct LpLdsPlan {
+  size_t fixed, shared, per_wave;
+};
+LpLdsPlan lp_lds_plan(const Geom &g, int which) {
+  const uint32_t npass = (g.npriv + 15u) / 16u, pstride = (2u * g.npriv * 64u + 15u) & ~15u;
+  LpLdsPlan p;
+  p.fixed = sizeof(AesLds) + (g.precision == SF_BF16 ? sizeof(LpLds<true>) : sizeof(LpLds<false>));
+  p.shared = which == 0 ? 64u * npass * sizeof(LpQ2) : 0u;
+  p.per_wave = (size_t)kGroup * pstride + (which == 0 ? (size_t)64u * g.npub : 0u);
+  return p;
+}
+
+// resident (the default): one resident generation of workgroups, each wave
+// walking pairs of tiles; otherwise one pair of tiles per wave.
+int lp_grid(const DeviceState &ds, const void *kernel, const Shape &sh, size_t lds, uint32_t ntiles) {
+  const uint32_t w = sh.waves;
+  if (!sh.resident) return (int)((ntiles + kGroup * w - 1) / (kGroup * w));
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * waves, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * (int)w, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
-  const uint32_t need = (ntiles + waves - 1) / waves;
+  const uint32_t need = (ntiles + w - 1) / w;
   const uint32_t cap = (uint32_t)ds.num_cu * (uint32_t)per_cu;
   return (int)(need < cap ? need : cap);
 }
 
-// Waves per workgroup: the largest of 8, 6, 4, 2, 1 whose LDS (static tables
-// plus the per-wave stages) leaves room for two workgroups per CU, else the
-// largest that fits at all.
-template <bool BF>
-int lp_waves(const DeviceState &ds, size_t shared, size_t per_wave, size_t *lds_out) {
-  static const int cand[] = {8, 6, 4, 2, 1};
-  const size_t fixed = sizeof(AesLds) + sizeof(LpLds<BF>);
-  const size_t cu_lds = 160u * 1024u;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int w : cand) {
-      const size_t dyn = shared + (size_t)w * per_wave;
-      if (fixed + dyn > ds.max_lds_per_block) continue;
-      if (pass == 0 && 2 * (fixed + dyn) > cu_lds) continue;
-      *lds_out = dyn;
-      return w;
-    }
-  return 0;
-}
-
-template <bool BF, class MP>
-int launch_frag(const DeviceState &ds, const LpArgs &a0, hipStream_t stream) {
+template <bool BF, class MP, bool kFrag>
+int launch(const DeviceState &ds, const LpArgs &a0, const Shape &sh, const LpLdsPlan &p, hipStream_t stream) {
   LpArgs a = a0;
-  const size_t shared = 64u * a.npass * sizeof(LpQ2);
-  const size_t per_wave = (size_t)kGroup * a.pstride + (size_t)64u * a.g.npub;
-  size_t lds = 0;
-  const int w = lp_waves<BF>(ds, shared, per_wave, &lds);
-  if (!w) return fail(SF_ENOTSUP, "selection needs more LDS per workgroup than the device offers in this form");
-  a.wave_lds = (uint32_t)per_wave;
-  const int grid = lp_grid(ds, (const void *)&lp_frag_kernel<BF, MP>, w, lds, a.g.ntiles);
-  hipLaunchKernelGGL((lp_frag_kernel<BF, MP>), dim3(grid), dim3(64 * w), lds, stream, a);
+  const size_t lds = p.shared + (size_t)sh.waves * p.per_wave;
+  a.wave_lds = (uint32_t)p.per_wave;
+  const void *k = kFrag ? (const void *)&lp_frag_kernel<BF, MP> : (const void *)&lp_defrag_kernel<BF, MP>;
+  const int grid = lp_grid(ds, k, sh, lds, a.g.ntiles);
+  if (kFrag)
+    hipLaunchKernelGGL((lp_frag_kernel<BF, MP>), dim3(grid), dim3(64 * sh.waves), lds, stream, a);
+  else
+    hipLaunchKernelGGL((lp_defrag_kernel<BF, MP>), dim3(grid), dim3(64 * sh.waves), lds, stream, a);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? SF_OK : hip_fail(e, "frag_lp kernel launch");
-}
-
-template <bool BF, class MP>
-int launch_defrag(const DeviceState &ds, const LpArgs &a0, hipStream_t stream) {
-  LpArgs a = a0;
-  const size_t per_wave = (size_t)kGroup * a.pstride;
-  size_t lds = 0;
-  const int w = lp_waves<BF>(ds, 0, per_wave, &lds);
-  if (!w) return fail(SF_ENOTSUP, "selection needs more LDS per workgroup than the device offers in this form");
-  a.wave_lds = (uint32_t)per_wave;
-  const int grid = lp_grid(ds, (const void *)&lp_defrag_kernel<BF, MP>, w, lds, a.g.ntiles);
-  hipLaunchKernelGGL((lp_defrag_kernel<BF, MP>), dim3(grid), dim3(64 * w), lds, stream, a);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? SF_OK : hip_fail(e, "defrag_lp kernel launch");
+  return e == hipSuccess ? SF_OK : hip_fail(e, kFrag ? "frag_lp kernel launch" : "defrag_lp kernel launch");
 }
 
 template <bool BF, bool kFrag>
-int dispatch(const DeviceState &ds, const LpArgs &a, hipStream_t stream) {
-  auto go = [&](auto mp) {
-    using MP = decltype(mp);
-    return kFrag ? launch_frag<BF, MP>(ds, a, stream) : launch_defrag<BF, MP>(ds, a, stream);
-  };
+int dispatch(const DeviceState &ds, const LpArgs &a, const Shape &sh, const LpLdsPlan &p, hipStream_t stream) {
+  auto go = [&](auto mp) { return launch<BF, decltype(mp), kFrag>(ds, a, sh, p, stream); };
   switch (a.g.mask) {
     case (1ull << 2) - 1: return go(MaskPrefix<2>{});
     case (1ull << 3) - 1: return go(MaskPrefix<3>{});
@@ -935,6 +918,18 @@ int dispatch(const DeviceState &ds, const LpArgs &a, hipStream_t stream) {
     case (1ull << 10) - 1: return go(MaskPrefix<10>{});
     default: return go(MaskRuntime{});
   }
+}
+
+// The resolved shape, or SF_ENOTSUP if its LDS does not fit a workgroup.
+int lp_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
+  *out = in;
+  if (!out->waves) {
+    out->waves = lp_default_waves(ds, g, which);
+    if (!out->waves) return fail(SF_ENOTSUP, "selection needs more LDS per workgroup than the device offers in this form");
+  }
+  if (out->waves > 8u || lp_lds_bytes(g, which, out->waves) > ds.max_lds_per_block)
+    return fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
+  return SF_OK;
 }
 
 LpArgs lp_args(const DeviceState &ds, const Geom &g, const uint8_t *pix, const sf_exceptions *exc,
@@ -969,25 +964,53 @@ LpArgs lp_args(const DeviceState &ds, const Geom &g, const uint8_t *pix, const s
 
 }  // namespace
 
+size_t lp_lds_bytes(const Geom &g, int which, uint32_t waves) {
+  const LpLdsPlan p = lp_lds_plan(g, which);
+  return p.fixed + p.shared + (size_t)waves * p.per_wave;
+}
+
+// Waves per workgroup: the largest of 8, 6, 4, 2, 1 whose LDS leaves room for
+// two workgroups per CU, else the largest that fits at all (0: none fits).
+uint32_t lp_default_waves(const DeviceState &ds, const Geom &g, int which) {
+  static const uint32_t cand[] = {8, 6, 4, 2, 1};
+  const size_t cu_lds = 160u * 1024u;
+  for (int pass = 0; pass < 2; ++pass)
+    for (uint32_t w : cand) {
+      const size_t b = lp_lds_bytes(g, which, w);
+      if (b > ds.max_lds_per_block) continue;
+      if (pass == 0 && 2 * b > cu_lds) continue;
+      return w;
+    }
+  return 0;
+}
+
 int launch_frag_lp(const DeviceState &ds, const Geom &g, const uint8_t *pix, void *pub, uint8_t *priv,
                    const sf_exceptions *exc, uint8_t *residual, const AesArgs &aes, uint32_t *status,
-                   hipStream_t stream) {
+                   const Shape &shape, hipStream_t stream) {
+  Shape sh;
+  if (int rc = lp_shape(ds, g, 0, shape, &sh)) return rc;
   LpArgs a = lp_args(ds, g, pix, exc, aes, status);
   a.pub = (uint16_t *)pub;
   a.priv = priv;
   a.resid = residual;
-  return g.precision == SF_BF16 ? dispatch<true, true>(ds, a, stream) : dispatch<false, true>(ds, a, stream);
+  const LpLdsPlan p = lp_lds_plan(g, 0);
+  return g.precision == SF_BF16 ? dispatch<true, true>(ds, a, sh, p, stream)
+                                : dispatch<false, true>(ds, a, sh, p, stream);
 }
 
 int launch_defrag_lp(const DeviceState &ds, const Geom &g, const void *pub, const uint8_t *priv,
                      const sf_exceptions *exc, const uint8_t *residual, const AesArgs &aes, uint8_t *pix,
-                     uint32_t *status, hipStream_t stream) {
+                     uint32_t *status, const Shape &shape, hipStream_t stream) {
+  Shape sh;
+  if (int rc = lp_shape(ds, g, 1, shape, &sh)) return rc;
   LpArgs a = lp_args(ds, g, nullptr, exc, aes, status);
   a.pub = (uint16_t *)pub;
   a.priv = (uint8_t *)priv;
   a.resid = (uint8_t *)residual;
   a.pix_out = pix;
-  return g.precision == SF_BF16 ? dispatch<true, false>(ds, a, stream) : dispatch<false, false>(ds, a, stream);
+  const LpLdsPlan p = lp_lds_plan(g, 1);
+  return g.precision == SF_BF16 ? dispatch<true, false>(ds, a, sh, p, stream)
+                                : dispatch<false, false>(ds, a, sh, p, stream);
 }
 
 }  // namespace sf

@@ -9,8 +9,9 @@
 namespace sf {
 namespace {
 
-constexpr int kWaves = 2;  // 2 waves per workgroup measured best (1, 2, 4, 8 tried)
-constexpr int kThreads = 64 * kWaves;
+// Workgroups of 1 to 8 wavefronts (the launch shape; 2 is the default).
+constexpr int kMaxWaves = 8;
+constexpr int kMaxThreads = 64 * kMaxWaves;
 
 struct FragKernelArgs {
   TileGeom g;
@@ -48,13 +49,14 @@ struct DefragKernelArgs {
 // 16 private AC coefficients); each wave then owns kQ2StageBytes of LDS
 // after its private-byte staging area.
 template <class MP, bool kQ2Mfma>
-__global__ __launch_bounds__(kThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kernel(FragKernelArgs a) {
+__global__ __launch_bounds__(kMaxThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kernel(FragKernelArgs a) {
   __shared__ AesLds s_aes;
   __shared__ Q2Operands s_q2[kQ2Mfma ? 64 : 1];  // B operand per lane (same for every wave)
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
+  const uint32_t nw = blockDim.x >> 6;
+  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, blockDim.x);
   if constexpr (kQ2Mfma)
     if (threadIdx.x < 64) s_q2[lane] = q2_operands(a.o.q2, private_ac<MP>(a.g.mask, lane & 15), lane);
   __syncthreads();
@@ -62,8 +64,8 @@ __global__ __launch_bounds__(kThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kern
   uint8_t *lp = s_dyn + wave * (a.lds_priv_bytes + kStage);
   uint8_t *q2stage = lp + a.lds_priv_bytes;
   const Q2Operands *Q = &s_q2[kQ2Mfma ? lane : 0];
-  const uint32_t stride = gridDim.x * kWaves;
-  uint32_t t = blockIdx.x * kWaves + wave;
+  const uint32_t stride = gridDim.x * nw;
+  uint32_t t = blockIdx.x * nw + wave;
   if (t >= a.g.ntiles) return;
 #if SF_FRAG_PREFETCH
   TileLane L = tile_lane(a.g, t, lane);
@@ -117,49 +119,79 @@ __global__ __launch_bounds__(kThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kern
 }
 
 template <class MP>
-__global__ __launch_bounds__(kThreads, SF_DEFRAG_WAVES_PER_EU) void defrag_fp32_kernel(DefragKernelArgs a) {
+__global__ __launch_bounds__(kMaxThreads, SF_DEFRAG_WAVES_PER_EU) void defrag_fp32_kernel(DefragKernelArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
   const int lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, kThreads);
+  const uint32_t nw = blockDim.x >> 6;
+  if (a.aes.enabled) aes_load_tables(s_aes, a.aes_t0, a.aes.key, threadIdx.x, blockDim.x);
   __syncthreads();
   uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
-  const uint32_t stride = gridDim.x * kWaves;
-  for (uint32_t t = blockIdx.x * kWaves + wave; t < a.g.ntiles; t += stride)
+  const uint32_t stride = gridDim.x * nw;
+  for (uint32_t t = blockIdx.x * nw + wave; t < a.g.ntiles; t += stride)
     defrag_tile<MP>(a.g, a.in, t, tile_lane(a.g, t, lane), lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi,
                     a.aes.ctr_lo, a.K);
 }
 
 uint32_t lds_priv_bytes(const Geom &g) { return (2u * g.npriv * 64u + 15u) & ~15u; }
 
-// One tile per wave: the hardware dispatcher keeps every SIMD at its
-// occupancy limit and refills it as waves finish, which measured faster than
-// resident waves looping over tiles (the kernels still loop if the grid is
-// ever capped).  Beyond 2^31 - 1 workgroups the grid is capped at that.
-int grid_for(const DeviceState &, const void *, size_t, uint32_t ntiles) {
-  const uint64_t need = ((uint64_t)ntiles + kWaves - 1) / kWaves;
+// resident = 0 (the default): one tile per wave; the hardware dispatcher
+// keeps every SIMD at its occupancy limit and refills it as waves finish,
+// which measured faster than resident waves looping over tiles on the large
+// images.  resident = 1: as many workgroups as the device holds at once,
+// looping.  Beyond 2^31 - 1 workgroups the grid is capped at that (the
+// kernels loop).
+int grid_for(const DeviceState &ds, const void *kernel, const Shape &sh, size_t lds, uint32_t ntiles) {
+  uint64_t need = ((uint64_t)ntiles + sh.waves - 1) / sh.waves;
+  if (sh.resident) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * (int)sh.waves, lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    const uint64_t cap = (uint64_t)ds.num_cu * (uint64_t)per_cu;
+    need = need < cap ? need : cap;
+  }
   return (int)(need < 0x7fffffffu ? need : 0x7fffffffu);
 }
 
+bool q2_on_mfma(const Geom &g) { return __builtin_popcountll(g.mask & ~1ull) <= kQ2MfmaMaxAc; }
+
 template <class MP, bool kQ2Mfma>
-int launch_frag_mp(const DeviceState &ds, const FragKernelArgs &a, hipStream_t stream) {
-  const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + (kQ2Mfma ? kQ2StageBytes : 0u));
-  const int grid = grid_for(ds, (const void *)&frag_fp32_kernel<MP, kQ2Mfma>, lds, a.g.ntiles);
-  hipLaunchKernelGGL((frag_fp32_kernel<MP, kQ2Mfma>), dim3(grid), dim3(kThreads), lds, stream, a);
+int launch_frag_mp(const DeviceState &ds, const FragKernelArgs &a, const Shape &sh, hipStream_t stream) {
+  const size_t lds = (size_t)sh.waves * (a.lds_priv_bytes + (kQ2Mfma ? kQ2StageBytes : 0u));
+  const int grid = grid_for(ds, (const void *)&frag_fp32_kernel<MP, kQ2Mfma>, sh, lds, a.g.ntiles);
+  hipLaunchKernelGGL((frag_fp32_kernel<MP, kQ2Mfma>), dim3(grid), dim3(64 * sh.waves), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "frag kernel launch");
 }
 
 template <class MP>
-int launch_defrag_mp(const DeviceState &ds, const DefragKernelArgs &a, size_t lds, hipStream_t stream) {
-  const int grid = grid_for(ds, (const void *)&defrag_fp32_kernel<MP>, lds, a.g.ntiles);
-  hipLaunchKernelGGL(defrag_fp32_kernel<MP>, dim3(grid), dim3(kThreads), lds, stream, a);
+int launch_defrag_mp(const DeviceState &ds, const DefragKernelArgs &a, const Shape &sh, hipStream_t stream) {
+  const size_t lds = (size_t)sh.waves * a.lds_priv_bytes;
+  const int grid = grid_for(ds, (const void *)&defrag_fp32_kernel<MP>, sh, lds, a.g.ntiles);
+  hipLaunchKernelGGL(defrag_fp32_kernel<MP>, dim3(grid), dim3(64 * sh.waves), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "defrag kernel launch");
 }
 
+// The resolved shape, or SF_ENOTSUP if its LDS does not fit a workgroup.
+int plain_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
+  *out = in;
+  if (!out->waves) out->waves = kPlainDefaultWaves;
+  if (out->waves > (uint32_t)kMaxWaves || plain_lds_bytes(g, which, out->waves) > ds.max_lds_per_block)
+    return fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
+  return SF_OK;
+}
+
 }  // namespace
+
+size_t plain_lds_bytes(const Geom &g, int which, uint32_t waves) {
+  const size_t priv = lds_priv_bytes(g);
+  if (which == 1) return sizeof(AesLds) + waves * priv;
+  const bool mf = q2_on_mfma(g);
+  return sizeof(AesLds) + (mf ? 64u : 1u) * sizeof(Q2Operands) + waves * (priv + (mf ? kQ2StageBytes : 0u));
+}
 
 ExcSlots exc_slots(const Geom &g, const sf_exceptions *exc) {
   ExcSlots s{};
@@ -175,7 +207,10 @@ ExcSlots exc_slots(const Geom &g, const sf_exceptions *exc) {
 }
 
 int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, float *pub, uint8_t *priv,
-                     const sf_exceptions *exc, const AesArgs &aes, uint32_t *status, hipStream_t stream) {
+                     const sf_exceptions *exc, const AesArgs &aes, uint32_t *status, const Shape &shape,
+                     hipStream_t stream) {
+  Shape sh;
+  if (int rc = plain_shape(ds, g, 0, shape, &sh)) return rc;
   FragKernelArgs a;
   a.g = tile_geom(g, pix);
   a.o.pub = pub;
@@ -191,18 +226,21 @@ int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, f
   // compile-time selections for DC + k AC, k in {1, 2, 5, 9}; any other mask
   // at run time, on the matrix cores while at most 16 AC coefficients are private
   switch (g.mask) {
-    case (1ull << 2) - 1: return launch_frag_mp<MaskPrefix<2>, true>(ds, a, stream);
-    case (1ull << 3) - 1: return launch_frag_mp<MaskPrefix<3>, true>(ds, a, stream);
-    case (1ull << 6) - 1: return launch_frag_mp<MaskPrefix<6>, true>(ds, a, stream);
-    case (1ull << 10) - 1: return launch_frag_mp<MaskPrefix<10>, true>(ds, a, stream);
+    case (1ull << 2) - 1: return launch_frag_mp<MaskPrefix<2>, true>(ds, a, sh, stream);
+    case (1ull << 3) - 1: return launch_frag_mp<MaskPrefix<3>, true>(ds, a, sh, stream);
+    case (1ull << 6) - 1: return launch_frag_mp<MaskPrefix<6>, true>(ds, a, sh, stream);
+    case (1ull << 10) - 1: return launch_frag_mp<MaskPrefix<10>, true>(ds, a, sh, stream);
     default:
-      if (__builtin_popcountll(g.mask & ~1ull) <= kQ2MfmaMaxAc) return launch_frag_mp<MaskRuntime, true>(ds, a, stream);
-      return launch_frag_mp<MaskRuntime, false>(ds, a, stream);
+      if (q2_on_mfma(g)) return launch_frag_mp<MaskRuntime, true>(ds, a, sh, stream);
+      return launch_frag_mp<MaskRuntime, false>(ds, a, sh, stream);
   }
 }
 
 int launch_defrag_fp32(const DeviceState &ds, const Geom &g, const float *pub, const uint8_t *priv,
-                       const sf_exceptions *exc, const AesArgs &aes, uint8_t *pix, hipStream_t stream) {
+                       const sf_exceptions *exc, const AesArgs &aes, uint8_t *pix, const Shape &shape,
+                       hipStream_t stream) {
+  Shape sh;
+  if (int rc = plain_shape(ds, g, 1, shape, &sh)) return rc;
   DefragKernelArgs a;
   a.g = tile_geom(g, nullptr);
   a.in.pix_out = pix;
@@ -213,13 +251,12 @@ int launch_defrag_fp32(const DeviceState &ds, const Geom &g, const float *pub, c
   a.aes = aes;
   a.K = host_tables().dct;
   a.lds_priv_bytes = lds_priv_bytes(g);
-  const size_t lds = (size_t)kWaves * a.lds_priv_bytes;
   switch (g.mask) {
-    case (1ull << 2) - 1: return launch_defrag_mp<MaskPrefix<2>>(ds, a, lds, stream);
-    case (1ull << 3) - 1: return launch_defrag_mp<MaskPrefix<3>>(ds, a, lds, stream);
-    case (1ull << 6) - 1: return launch_defrag_mp<MaskPrefix<6>>(ds, a, lds, stream);
-    case (1ull << 10) - 1: return launch_defrag_mp<MaskPrefix<10>>(ds, a, lds, stream);
-    default: return launch_defrag_mp<MaskRuntime>(ds, a, lds, stream);
+    case (1ull << 2) - 1: return launch_defrag_mp<MaskPrefix<2>>(ds, a, sh, stream);
+    case (1ull << 3) - 1: return launch_defrag_mp<MaskPrefix<3>>(ds, a, sh, stream);
+    case (1ull << 6) - 1: return launch_defrag_mp<MaskPrefix<6>>(ds, a, sh, stream);
+    case (1ull << 10) - 1: return launch_defrag_mp<MaskPrefix<10>>(ds, a, sh, stream);
+    default: return launch_defrag_mp<MaskRuntime>(ds, a, sh, stream);
   }
 }
 

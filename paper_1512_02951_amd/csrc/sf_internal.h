@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "sefrag.h"
 #include "sf_device.h"
@@ -38,6 +41,14 @@ void aes_expand_key(const uint8_t key[16], uint32_t rk[44]);
 float cert_threshold();
 bool mask_needs_check(uint64_t mask);
 
+// Launch shape of the single-image kernels (resolved: waves >= 1).
+struct Shape {
+  uint32_t waves;     // wavefronts per workgroup
+  uint32_t resident;  // 1: one resident generation of workgroups loops over the tiles
+};
+// (precision, private mask, size class, direction)
+using ShapeKey = std::tuple<uint32_t, uint64_t, uint32_t, int>;
+
 // Per-device state: device copies of the tables.
 struct DeviceState {
   int device = -1;
@@ -47,6 +58,8 @@ struct DeviceState {
   uint32_t *d_lp = nullptr;  // kLpTables x kLpTableWords
   size_t max_lds_per_block = 65536;
   void *d_sm_scratch = nullptr;  // this device's copy of the soft-mask scratch array
+  std::mutex shape_mu;           // guards shapes
+  std::map<ShapeKey, Shape> shapes;  // tuned or set launch shapes
 };
 // Lazily initialise the current device; returns SF_OK or an error code.
 int device_state(DeviceState **out);
@@ -83,19 +96,32 @@ struct ExcLayout {
 ExcLayout exc_layout(const Geom &g, uint32_t per_tile);
 constexpr uint32_t kMaxExcPerTile = 4096;
 
+// Launch shapes (api.hip): the stored shape of (g, which = 0 frag / 1
+// defrag), else the form's default (waves = 0: chosen by the launcher).
+Shape stored_shape(DeviceState &ds, const Geom &g, int which);
+// Workgroup LDS (static + dynamic) of a shape, for the fit check (plain.hip,
+// lp.hip).
+size_t plain_lds_bytes(const Geom &g, int which, uint32_t waves);
+size_t lp_lds_bytes(const Geom &g, int which, uint32_t waves);
+// Default wavefronts per workgroup of the reduced-precision kernels.
+uint32_t lp_default_waves(const DeviceState &ds, const Geom &g, int which);
+constexpr uint32_t kPlainDefaultWaves = 2;
+
 // Launchers (plain.hip, aes.hip).
 int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, float *pub, uint8_t *priv,
-                     const sf_exceptions *exc, const AesArgs &aes, uint32_t *status, hipStream_t stream);
+                     const sf_exceptions *exc, const AesArgs &aes, uint32_t *status, const Shape &sh,
+                     hipStream_t stream);
 int launch_defrag_fp32(const DeviceState &ds, const Geom &g, const float *pub, const uint8_t *priv,
-                       const sf_exceptions *exc, const AesArgs &aes, uint8_t *pix, hipStream_t stream);
+                       const sf_exceptions *exc, const AesArgs &aes, uint8_t *pix, const Shape &sh,
+                       hipStream_t stream);
 // Reduced-precision (MFMA fp16 / bf16 + 2-bit residual codes and exception
 // slots) form (lp.hip).
 int launch_frag_lp(const DeviceState &ds, const Geom &g, const uint8_t *pix, void *pub, uint8_t *priv,
                    const sf_exceptions *exc, uint8_t *residual, const AesArgs &aes, uint32_t *status,
-                   hipStream_t stream);
+                   const Shape &sh, hipStream_t stream);
 int launch_defrag_lp(const DeviceState &ds, const Geom &g, const void *pub, const uint8_t *priv,
                      const sf_exceptions *exc, const uint8_t *residual, const AesArgs &aes, uint8_t *pix,
-                     uint32_t *status, hipStream_t stream);
+                     uint32_t *status, const Shape &sh, hipStream_t stream);
 // Batched form (batch.hip).
 size_t batch_workspace_bytes(uint32_t n);
 int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, const uint8_t *key, void *d_ws,

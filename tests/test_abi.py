@@ -110,3 +110,20 @@ def test_c_consumer_builds_against_the_header(tmp_path):
     # include/sefrag.h and the in-tree library; the GPU test runs it
     from c_abi_build import build_c_program
     assert os.path.exists(build_c_program(str(tmp_path)))
+
+
+def test_launch_shape_arguments_are_checked_on_the_host():
+    L = sf.lib()
+    d = sf.SfDesc(64, 64, 1, 0, 0x3F)
+    ok = sf.SfLaunchShape(2, 0)
+    for which, shape in ((2, ok), (-1, ok), (0, sf.SfLaunchShape(3, 0)), (1, sf.SfLaunchShape(16, 0)),
+                         (0, sf.SfLaunchShape(2, 2))):
+        assert L.sf_set_launch_shape(ctypes.byref(d), which, ctypes.byref(shape)) == sf.SF_EINVAL
+    assert L.sf_get_launch_shape(ctypes.byref(d), 0, None) == sf.SF_EINVAL
+    bad = sf.SfDesc(12, 64, 1, 0, 0x3F)
+    assert L.sf_set_launch_shape(ctypes.byref(bad), 0, ctypes.byref(ok)) == sf.SF_ESHAPE
+    exc = sf.SfExceptions(64, 4)
+    args = [ctypes.byref(exc), None, None, 64, None, None, None, None, None, None]
+    assert L.sf_tune_image(ctypes.byref(d), None, 64, 64, *args) == sf.SF_EINVAL  # no pixels
+    args[3] = None
+    assert L.sf_tune_image(ctypes.byref(d), 64, 64, 64, *args) == sf.SF_EINVAL  # no restored buffer
