@@ -198,12 +198,15 @@ int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *
 /* One launch shape.  Host struct. */
 typedef struct sf_launch_shape {
   uint32_t waves_per_group; /* wavefronts per workgroup: 1, 2, 4, 6 or 8;
-                               0 = the form's default (plain: 2; reduced
+                               0 = the form's default (plain: 4 for 8 or
+                               more private coefficients, else 2; reduced
                                precision: the largest that lets two
                                workgroups share a compute unit's LDS)      */
   uint32_t resident;        /* 1: one resident generation of workgroups
                                (as many as the device holds at once) loops
-                               over the tiles; 0: the grid gives each
+                               over the tiles (the default of the reduced
+                               precision, and of the plain form for 8 or
+                               more private coefficients); 0: the grid gives each
                                wavefront one tile (plain) or one pair of
                                tiles (reduced precision)                    */
 } sf_launch_shape;
@@ -224,9 +227,11 @@ int sf_set_launch_shape(const sf_desc *desc, int which, const sf_launch_shape *s
 int sf_get_launch_shape(const sf_desc *desc, int which, sf_launch_shape *out);
 
 /* sf_tune_image -- times frag_image and then defrag_image of the image in
- * every shape that fits (waves_per_group 1, 2, 4, 6, 8 x resident 0, 1),
- * three launches each after one untimed launch, on `stream`, and stores the
- * fastest of each direction as with sf_set_launch_shape.  Arguments as in
+ * every shape that fits (waves_per_group 1, 2, 4, 6, 8 x resident 0, 1) on
+ * `stream`: two rounds over the shapes, each shape one untimed and five
+ * timed launches per round, a shape's time the lower of its two round
+ * averages; stores the fastest of each direction as with
+ * sf_set_launch_shape.  Arguments as in
  * frag_image (d_pixels in; d_public, d_private, exc, d_residual out) plus
  * d_restored, the output of defrag_image (must not overlap the others).
  * Synchronous: returns when the timing is done; on return the fragments and

@@ -139,14 +139,14 @@ Shape stored_shape(DeviceState &ds, const Geom &g, int which) {
   std::lock_guard<std::mutex> lk(ds.shape_mu);
   auto it = ds.shapes.find(shape_key(g, which));
   if (it != ds.shapes.end()) return it->second;
-  return Shape{0u, g.precision == SF_FP32 ? 0u : 1u};
+  return Shape{0u, g.precision == SF_FP32 && !plain_heavy(g) ? 0u : 1u};
 }
 
 // The shape a launch of (g, which) would use, resolved (waves >= 1).
 static int resolved_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
   *out = in;
   if (g.precision == SF_FP32) {
-    if (!out->waves) out->waves = kPlainDefaultWaves;
+    if (!out->waves) out->waves = plain_default_waves(g);
     return plain_lds_bytes(g, which, out->waves) <= ds.max_lds_per_block
                ? SF_OK
                : fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
@@ -342,19 +342,35 @@ int sf_tune_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, 
     return hip_fail(he, "hipEventCreate");
   }
   static const uint32_t waves[] = {1, 2, 4, 6, 8};
+  constexpr int kRounds = 2, kTimed = 5;
   Shape best[2] = {};
   float best_ms[2] = {0.0f, 0.0f};
   for (int which = 0; which < 2 && rc == SF_OK; ++which) {
     // defrag is timed on fragments made in frag's chosen shape
     if (which == 1 && (rc = run(0, best[0]))) break;
-    bool any = false;
-    for (uint32_t res = 0; res < 2 && rc == SF_OK; ++res)
+    Shape cand[10];
+    float cand_ms[10];
+    int nc = 0;
+    for (uint32_t res = 0; res < 2; ++res)
       for (uint32_t w : waves) {
         Shape sh{w, res}, r;
-        if (resolved_shape(*ds, g, which, sh, &r)) continue;  // does not fit: not a candidate
-        if ((rc = run(which, sh))) break;
-        if ((he = hipEventRecord(e0, st)) != hipSuccess) { rc = hip_fail(he, "hipEventRecord"); break; }
-        for (int i = 0; i < 3 && rc == SF_OK; ++i) rc = run(which, sh);
+        if (resolved_shape(*ds, g, which, sh, &r) == SF_OK) {  // shapes that do not fit are no candidates
+          cand[nc] = sh;
+          cand_ms[nc++] = 0.0f;
+        }
+      }
+    if (!nc) {
+      rc = fail(SF_ENOTSUP, "no launch shape fits this selection on this device");
+      break;
+    }
+    for (int round = 0; round < kRounds && rc == SF_OK; ++round)
+      for (int c = 0; c < nc && rc == SF_OK; ++c) {
+        if ((rc = run(which, cand[c]))) break;
+        if ((he = hipEventRecord(e0, st)) != hipSuccess) {
+          rc = hip_fail(he, "hipEventRecord");
+          break;
+        }
+        for (int i = 0; i < kTimed && rc == SF_OK; ++i) rc = run(which, cand[c]);
         if (rc) break;
         float ms = 0.0f;
         if ((he = hipEventRecord(e1, st)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess ||
@@ -362,14 +378,15 @@ int sf_tune_image(const sf_desc *desc, const uint8_t *d_pixels, void *d_public, 
           rc = hip_fail(he, "timing a launch shape");
           break;
         }
-        ms /= 3.0f;
-        if (!any || ms < best_ms[which]) {
-          best[which] = sh;
-          best_ms[which] = ms;
-          any = true;
-        }
+        ms /= (float)kTimed;
+        if (round == 0 || ms < cand_ms[c]) cand_ms[c] = ms;
       }
-    if (rc == SF_OK && !any) rc = fail(SF_ENOTSUP, "no launch shape fits this selection on this device");
+    if (rc) break;
+    int b = 0;
+    for (int c = 1; c < nc; ++c)
+      if (cand_ms[c] < cand_ms[b]) b = c;
+    best[which] = cand[b];
+    best_ms[which] = cand_ms[b];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

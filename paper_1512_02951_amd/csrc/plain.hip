@@ -136,12 +136,10 @@ __global__ __launch_bounds__(kMaxThreads, SF_DEFRAG_WAVES_PER_EU) void defrag_fp
 
 uint32_t lds_priv_bytes(const Geom &g) { return (2u * g.npriv * 64u + 15u) & ~15u; }
 
-// resident = 0 (the default): one tile per wave; the hardware dispatcher
-// keeps every SIMD at its occupancy limit and refills it as waves finish,
-// which measured faster than resident waves looping over tiles on the large
-// images.  resident = 1: as many workgroups as the device holds at once,
-// looping.  Beyond 2^31 - 1 workgroups the grid is capped at that (the
-// kernels loop).
+// resident = 1: as many workgroups as the device holds at once, each wave
+// looping over tiles; resident = 0: one tile per wave, the hardware
+// dispatcher refilling SIMDs as waves finish.
+// Beyond 2^31 - 1 workgroups the grid is capped at that (the kernels loop).
 int grid_for(const DeviceState &ds, const void *kernel, const Shape &sh, size_t lds, uint32_t ntiles) {
   uint64_t need = ((uint64_t)ntiles + sh.waves - 1) / sh.waves;
   if (sh.resident) {
@@ -178,7 +176,7 @@ int launch_defrag_mp(const DeviceState &ds, const DefragKernelArgs &a, const Sha
 // The resolved shape, or SF_ENOTSUP if its LDS does not fit a workgroup.
 int plain_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
   *out = in;
-  if (!out->waves) out->waves = kPlainDefaultWaves;
+  if (!out->waves) out->waves = plain_default_waves(g);
   if (out->waves > (uint32_t)kMaxWaves || plain_lds_bytes(g, which, out->waves) > ds.max_lds_per_block)
     return fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
   return SF_OK;

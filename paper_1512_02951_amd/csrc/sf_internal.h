@@ -105,7 +105,12 @@ size_t plain_lds_bytes(const Geom &g, int which, uint32_t waves);
 size_t lp_lds_bytes(const Geom &g, int which, uint32_t waves);
 // Default wavefronts per workgroup of the reduced-precision kernels.
 uint32_t lp_default_waves(const DeviceState &ds, const Geom &g, int which);
-constexpr uint32_t kPlainDefaultWaves = 2;
+// Default shape of the plain kernels: 4 waves per workgroup, resident, for
+// selections of 8 or more private coefficients; 2 waves, one tile per wave,
+// for the lighter ones (measured on the 4096^2 RGB DC + 5 AC and the 8192^2
+// DC + 9 AC workloads).
+inline bool plain_heavy(const Geom &g) { return g.npriv >= 8; }
+inline uint32_t plain_default_waves(const Geom &g) { return plain_heavy(g) ? 4u : 2u; }
 
 // Launchers (plain.hip, aes.hip).
 int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, float *pub, uint8_t *priv,
