@@ -549,13 +549,20 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
         // cert_thr - sum_n E_n M_n of 1/2 (the rest of the certificate's
         // allowance bounds everything else); these go to the exception slots
         // whether or not they would actually round wrong
+        // corner_estimate gives the samples in the order g = 16 y + 2 x + s
+        // (sample 8 y + x for s = 0, 8 (7 - y) + x for s = 1, y < 4); each
+        // one shifts the sign of |e| - thr into a word (v_alignbit_b32), so
+        // after 32 samples sample g sits at bit 31 - g % 32 of word g / 32,
+        // and the bit is clear where |e| >= thr
         const float thr = o.cert_thr - sum_em;
         corner_estimate<MP>(dq, K, [&](auto pc, float e) {
-          constexpr int p = decltype(pc)::value;
-          const uint32_t miss = __builtin_fabsf(e) >= thr ? 1u : 0u;
-          uint32_t &acc = p < 32 ? bad_lo : bad_hi;
-          asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(acc) : "v"(miss), "i"(p & 31));
+          constexpr int p = decltype(pc)::value, row = p / 8, x = p % 8;
+          constexpr int gg = row < 4 ? 16 * row + 2 * x : 16 * (7 - row) + 2 * x + 1;
+          uint32_t &acc = gg < 32 ? bad_lo : bad_hi;
+          acc = __builtin_amdgcn_alignbit(acc, __float_as_uint(__builtin_fabsf(e) - thr), 31);
         });
+        bad_lo = ~bad_lo;
+        bad_hi = ~bad_hi;
       } else {
         idct8x8(c, K);
 #pragma unroll
@@ -572,8 +579,12 @@ __device__ __forceinline__ void frag_tile(const TileGeom &g, const FragOut &o, u
       if (!valid) bad = 0;
       uint32_t slot = wave_exclusive_scan((uint32_t)__builtin_popcountll(bad), lane, total);
       while (bad) {
-        const uint32_t p = (uint32_t)__builtin_ctzll(bad);
+        uint32_t p = (uint32_t)__builtin_ctzll(bad);
         bad &= bad - 1ull;
+        if constexpr (corner_selection<MP>()) {  // bit of sample g (see above) -> sample
+          const uint32_t gg = 32u * (p >> 5) + 31u - (p & 31u), y = gg >> 4, x = (gg >> 1) & 7u;
+          p = (gg & 1u) ? 8u * (7u - y) + x : 8u * y + x;
+        }
         if (slot < o.exc.per_tile) {
           const size_t e = (size_t)t * o.exc.per_tile + slot;
           o.exc.pos[e] = (uint16_t)(lane * 64 + p);
