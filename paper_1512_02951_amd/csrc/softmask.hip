@@ -46,6 +46,8 @@ __host__ __device__ inline SmGeom sm_geom(uint32_t B, uint32_t H, uint32_t W, ui
   g.blocks = (H / 8) * (W / 8);
   g.tiles = (g.blocks + 63) / 64;
   // enough workgroups to cover every CU about twice, at most one wave per tile
+  // (more workgroups measured slower, also for the statistics-only pass,
+  // whose registers would allow them)
   uint32_t want = (2 * num_cu + B - 1) / B;
   const uint32_t cap = (g.tiles + kWaves - 1) / kWaves;
   g.wg_per_image = want < 1 ? 1 : (want > cap ? cap : want);
@@ -74,12 +76,17 @@ __device__ __forceinline__ void load_fblock(const float *plane, uint32_t W, uint
   }
 }
 
+// P is written once per call: streaming (non-temporal) stores (measured 9 %
+// faster for the forward with P than default-policy stores; non-temporal
+// loads of x were slower).
+typedef float f4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_fblock(float *plane, uint32_t W, uint32_t org, const float (&c)[64]) {
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    *reinterpret_cast<float4 *>(plane + org + (size_t)r * W) = make_float4(c[8 * r], c[8 * r + 1], c[8 * r + 2], c[8 * r + 3]);
-    *reinterpret_cast<float4 *>(plane + org + (size_t)r * W + 4) =
-        make_float4(c[8 * r + 4], c[8 * r + 5], c[8 * r + 6], c[8 * r + 7]);
+    const f4v a = {c[8 * r], c[8 * r + 1], c[8 * r + 2], c[8 * r + 3]};
+    const f4v b = {c[8 * r + 4], c[8 * r + 5], c[8 * r + 6], c[8 * r + 7]};
+    __builtin_nontemporal_store(a, reinterpret_cast<f4v *>(plane + org + (size_t)r * W));
+    __builtin_nontemporal_store(b, reinterpret_cast<f4v *>(plane + org + (size_t)r * W + 4));
   }
 }
 
@@ -180,7 +187,10 @@ struct SmArgs {
   DctK K;
 };
 
-// Statistics per image: E_0 .. E_63, then sum x.
+// Statistics per image: E_0 .. E_63, then sum x; with kP also P.  Two
+// instantiations so that the statistics-only pass is not held to the
+// registers of the pass that keeps the coefficients for P.
+template <bool kP>
 __global__ __launch_bounds__(kThreads) void sm_forward_kernel(SmArgs a) {
   __shared__ float s_keep[64];
   if (threadIdx.x < 64) s_keep[threadIdx.x] = 1.0f - 1.0f / (1.0f + __expf(-a.logits[threadIdx.x]));
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void sm_forward_kernel(SmArgs a) {
     sx[0] += s;
     fdct8x8(c, a.K);
     e_acc += wave_reduce_scatter([&](int n) { return c[n] * c[n]; });
-    if (a.p_out) {
+    if constexpr (kP) {
       const float *keep = s_keep + opaque_zero();  // re-read per tile: not 64 live registers
 #pragma unroll
       for (int n = 0; n < 64; ++n) c[n] *= keep[n];
@@ -543,7 +553,10 @@ int softmask_forward(const DeviceState &ds, const float *x, uint32_t B, uint32_t
   a.logits = logits;
   a.partials = (double *)ws;
   a.K = host_tables().dct;
-  hipLaunchKernelGGL(sm_forward_kernel, dim3(g.wg_per_image, B), dim3(kThreads), 0, stream, a);
+  if (p_out)
+    hipLaunchKernelGGL(sm_forward_kernel<true>, dim3(g.wg_per_image, B), dim3(kThreads), 0, stream, a);
+  else
+    hipLaunchKernelGGL(sm_forward_kernel<false>, dim3(g.wg_per_image, B), dim3(kThreads), 0, stream, a);
   sm_launch_reduce(a.partials, B, g.wg_per_image, kStats, stats, stream);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "soft-mask forward launch");
