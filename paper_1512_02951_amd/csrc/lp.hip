@@ -131,7 +131,12 @@ __device__ __forceinline__ void nt_store8(void *p, uint32_t a, uint32_t b) {
 // Tiles whose private bytes go through one AES pass together: a tile of
 // DC + 9 AC holds 80 AES blocks, so two tiles fill three passes of 64 lanes
 // where one tile alone takes two.
-constexpr uint32_t kGroup = 2;
+// Tiles whose private strings go through the cipher together: pairs in
+// frag (DC + 9 AC: 160 AES blocks in 3 passes of 64 lanes), single tiles
+// in defrag (80 blocks: one pass and a quad-lane pass for the last 16),
+// which measured 2-4 us per 8192^2 image faster for defrag and slower for
+// frag.  The fragment layout does not depend on the grouping.
+constexpr uint32_t kFragGroup = 2, kDefragGroup = 1;
 
 template <bool BF>
 __device__ __forceinline__ f32x16 mfma(const uint4 &a, const uint4 &b, const f32x16 &c) {
@@ -317,31 +322,78 @@ struct LpArgs {
   uint32_t plist[16];      // natural indices of the private positions, 4 per word
 };
 
-// LDS of one wave: kGroup private stages (int16 [rank][block], the tile's
-// private byte string), then the public stage of one half (npub rows of
-// 64 bytes: 32 blocks of a rank).
+// LDS of one wave: one private stage per tile of its group (int16
+// [rank][block], the tile's private byte string), then (frag) the public
+// stage of one half (npub rows of 64 bytes: 32 blocks of a rank).
 struct WaveLds {
   uint8_t *priv;
   uint8_t *pub;
 };
 
 // The tile's private byte string is AES-CTR encrypted (frag) or decrypted
-// (defrag) for up to kGroup tiles at once: lane i of a pass takes AES block
-// a = 64 pass + i of the concatenated tiles.  Tile t's bytes start at byte
-// 128 P t of the fragment, i.e. counter 8 P t.
-static_assert(kGroup == 2, "tile groups are pairs");
+// (defrag) for the tiles of a group at once: lane i of a pass takes AES
+// block a = 64 pass + i of the concatenated tiles.  Tile t's bytes start at
+// byte 128 P t of the fragment, i.e. counter 8 P t.
 struct TileGroup {
   uint32_t n;         // tiles in the group (1 or 2)
   uint32_t t0, t1;    // the tiles
   uint32_t nb0, nb1;  // blocks in each tile
 };
 
+// AES blocks a = first + lane / 4 of the group, one per quad of lanes
+// (aes_encrypt_quad), 4 bytes per lane.  Called by the whole wave, with the
+// cipher on.
+template <bool kEncrypt, int LPB = 4>
+__device__ __forceinline__ void group_ctr_tail(const TileGroup &G, const WaveLds &W, uint32_t pstride, uint8_t *gpriv,
+                                               uint32_t npriv, int lane, const AesLds &s_aes, const AesArgs &aes,
+                                               uint32_t first, uint32_t n0, uint32_t total) {
+  constexpr uint32_t WB = 16u / LPB;
+  const uint32_t a = first + (uint32_t)lane / LPB, part = (uint32_t)lane % LPB;
+  const bool live = a < total;
+  const bool second = a >= n0;
+  const uint32_t i = second ? a - n0 : a;
+  const uint32_t t = second ? G.t1 : G.t0;
+  const uint32_t tbytes = 2u * npriv * (second ? G.nb1 : G.nb0);
+  const uint32_t o = 16u * i + WB * part;
+  uint8_t *lp = W.priv + (second ? pstride : 0u) + o;
+  uint8_t *gp = gpriv + (uint64_t)t * 128u * npriv + o;
+  uint32_t v[WB / 4];
+#pragma unroll
+  for (uint32_t k = 0; k < WB / 4; ++k) v[k] = 0u;
+  if (live) {
+    if (kEncrypt || o + WB <= tbytes) {
+      const uint8_t *src = kEncrypt ? (const uint8_t *)lp : (const uint8_t *)gp;
+#pragma unroll
+      for (uint32_t k = 0; k < WB / 4; ++k) v[k] = reinterpret_cast<const uint32_t *>(src)[k];
+    } else {  // the fragment's final, partial AES block: never read past its end
+      for (uint32_t j = 0; j + o < tbytes; ++j) v[j >> 2] |= (uint32_t)gp[j] << (8u * (j & 3u));
+    }
+  }
+  uint32_t w[4];
+  aes_counter(aes.ctr_hi, aes.ctr_lo, (uint64_t)t * 8u * npriv + i, w[0], w[1], w[2], w[3]);
+  static_assert(LPB == 4, "one block per quad of lanes");
+  v[0] ^= aes_encrypt_quad(part == 0 ? w[0] : part == 1 ? w[1] : part == 2 ? w[2] : w[3], part, s_aes);
+  if (live) {
+    if (!kEncrypt || o + WB <= tbytes) {
+      uint8_t *dst = kEncrypt ? gp : lp;
+#pragma unroll
+      for (uint32_t k = 0; k < WB / 4; ++k) reinterpret_cast<uint32_t *>(dst)[k] = v[k];
+    } else {
+      for (uint32_t j = 0; j + o < tbytes; ++j) gp[j] = (uint8_t)(v[j >> 2] >> (8u * (j & 3u)));
+    }
+  }
+}
+
+// Whole passes of 64 AES blocks take one block per lane; a last pass of at
+// most 16 blocks takes one block per quad of lanes.
 template <bool kEncrypt>
 __device__ __forceinline__ void group_ctr(const TileGroup &G, const WaveLds &W, uint32_t pstride, uint8_t *gpriv,
                                           uint32_t npriv, int lane, const AesLds &s_aes, const AesArgs &aes) {
   const uint32_t n0 = (2u * npriv * G.nb0 + 15u) / 16u;
   const uint32_t total = n0 + (G.n > 1 ? (2u * npriv * G.nb1 + 15u) / 16u : 0u);
-  for (uint32_t a = (uint32_t)lane; a < total; a += 64u) {
+  const uint32_t rem = total & 63u;
+  const uint32_t nrow = aes.enabled && rem != 0u && rem <= 16u ? total - rem : total;  // wave-uniform
+  for (uint32_t a = (uint32_t)lane; a < nrow; a += 64u) {
     const bool second = a >= n0;
     const uint32_t i = second ? a - n0 : a;
     const uint32_t t = second ? G.t1 : G.t0;
@@ -376,6 +428,7 @@ __device__ __forceinline__ void group_ctr(const TileGroup &G, const WaveLds &W, 
       for (uint32_t j = 0; j < tbytes - 16u * i; ++j) gp[j] = (uint8_t)(w[j >> 2] >> (8u * (j & 3u)));
     }
   }
+  if (nrow != total) group_ctr_tail<kEncrypt>(G, W, pstride, gpriv, npriv, lane, s_aes, aes, nrow, n0, total);
 }
 
 // The eight row words (columns 4h .. 4h + 3) of the lane's block in one half;
@@ -522,7 +575,7 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
   __syncthreads();
   WaveLds W;
   W.priv = s_dyn + 64u * a.npass * sizeof(LpQ2) + wave * a.wave_lds;
-  W.pub = W.priv + kGroup * a.pstride;
+  W.pub = W.priv + kFragGroup * a.pstride;
   const uint64_t mask = mask_of<MP>(g);
   const uint32_t h = (uint32_t)lane >> 5, jl = (uint32_t)lane & 31u;
   const uint32_t stride = gridDim.x * nw;
@@ -537,7 +590,7 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
   while (t < g.ntiles) {
     TileGroup G;
     G.n = 0;
-    for (uint32_t gi = 0; gi < kGroup && t < g.ntiles; ++gi, t += stride) {
+    for (uint32_t gi = 0; gi < kFragGroup && t < g.ntiles; ++gi, t += stride) {
       const uint64_t b0 = (uint64_t)t * 64u;
       const uint32_t ntb = (uint32_t)min<uint64_t>(64u, g.nb - b0);
       if (gi == 0) {
@@ -763,7 +816,7 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(L
     G.t0 = t0;
     G.nb0 = (uint32_t)min<uint64_t>(64u, g.nb - (uint64_t)t0 * 64u);
     G.t1 = t0 + stride;
-    G.n = G.t1 < g.ntiles ? 2u : 1u;
+    G.n = kDefragGroup > 1 && G.t1 < g.ntiles ? 2u : 1u;
     G.nb1 = G.n > 1 ? (uint32_t)min<uint64_t>(64u, g.nb - (uint64_t)G.t1 * 64u) : 0u;
     t0 += G.n * stride;
     group_ctr<false>(G, W, a.pstride, a.priv, g.npriv, lane, s_aes, a.aes);
@@ -877,15 +930,15 @@ LpLdsPlan lp_lds_plan(const Geom &g, int which) {
   LpLdsPlan p;
   p.fixed = sizeof(AesLds) + (g.precision == SF_BF16 ? sizeof(LpLds<true>) : sizeof(LpLds<false>));
   p.shared = which == 0 ? 64u * npass * sizeof(LpQ2) : 0u;
-  p.per_wave = (size_t)kGroup * pstride + (which == 0 ? (size_t)64u * g.npub : 0u);
+  p.per_wave = (size_t)(which == 0 ? kFragGroup : kDefragGroup) * pstride + (which == 0 ? (size_t)64u * g.npub : 0u);
   return p;
 }
 
 // resident (the default): one resident generation of workgroups, each wave
-// walking pairs of tiles; otherwise one pair of tiles per wave.
-int lp_grid(const DeviceState &ds, const void *kernel, const Shape &sh, size_t lds, uint32_t ntiles) {
+// walking groups of tiles; otherwise one group of `group` tiles per wave.
+int lp_grid(const DeviceState &ds, const void *kernel, const Shape &sh, size_t lds, uint32_t ntiles, uint32_t group) {
   const uint32_t w = sh.waves;
-  if (!sh.resident) return (int)((ntiles + kGroup * w - 1) / (kGroup * w));
+  if (!sh.resident) return (int)((ntiles + group * w - 1) / (group * w));
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * (int)w, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
@@ -900,7 +953,7 @@ int launch(const DeviceState &ds, const LpArgs &a0, const Shape &sh, const LpLds
   const size_t lds = p.shared + (size_t)sh.waves * p.per_wave;
   a.wave_lds = (uint32_t)p.per_wave;
   const void *k = kFrag ? (const void *)&lp_frag_kernel<BF, MP> : (const void *)&lp_defrag_kernel<BF, MP>;
-  const int grid = lp_grid(ds, k, sh, lds, a.g.ntiles);
+  const int grid = lp_grid(ds, k, sh, lds, a.g.ntiles, kFrag ? kFragGroup : kDefragGroup);
   if (kFrag)
     hipLaunchKernelGGL((lp_frag_kernel<BF, MP>), dim3(grid), dim3(64 * sh.waves), lds, stream, a);
   else
