@@ -96,3 +96,11 @@ def test_cpu_baseline_fields():
     assert r["kind"] == "oracle" and r["unit"] == "MP/s" and r["cores"] >= 1
     assert r["value"] > 0 and r["frag_MP/s"] > 0 and r["defrag_MP/s"] > 0
     assert r["single_thread"]["MP/s"] > 0 and r["cpu_model"]
+
+
+def test_cpu_fast_context_fields():
+    r = bench.cpu_fast_context()
+    assert r["frag_MP/s"] > 0 and r["defrag_MP/s"] > 0 and r["threads"] >= 1
+    assert "not exact" in r["kind"]
+    # rounding the private coefficients moves a sample by at most 1
+    assert r["samples_off_by_more_than_1"] == 0

@@ -40,3 +40,4 @@ def test_bench_prints_one_contract_line():
     assert r["achieved"] == pytest.approx(r["bytes_per_launch"] / (t * 1e-3) / 1e9, rel=1e-3)
     assert d["frag_burst_ms"] > 0 and d["defrag_burst_ms"] > 0
     assert d["warm_ms_per_step"] > 0 and d["graph_replay_ms_per_step"] > 0
+    assert 0 < d["median_ms_per_step"] < 10 * d["ms_per_step"]
