@@ -89,6 +89,24 @@ int main(void) {
     ok = 0;
   }
 
+  /* launch shapes: tune, read back, round trip in the tuned shapes, forget */
+  {
+    sf_launch_shape bf, bd, got;
+    float fms = 0.0f, dms = 0.0f;
+    check(sf_tune_image(&d, d_img, d_pub, d_priv, &exc, NULL, &aes, d_out, d_status, NULL, &bf, &bd, &fms, &dms),
+          "sf_tune_image");
+    ok &= compare(d_out, img, "plain DC+5AC, tuned shapes");
+    check(sf_get_launch_shape(&d, 0, &got), "sf_get_launch_shape");
+    if (got.waves_per_group != bf.waves_per_group || got.resident != bf.resident || !(fms > 0.0f) || !(dms > 0.0f)) {
+      fprintf(stderr, "tuned shape not stored\n");
+      ok = 0;
+    }
+    check(defrag_image(&d, d_pub, d_priv, &exc, NULL, &aes, d_out, d_status, NULL), "defrag_image tuned");
+    ok &= compare(d_out, img, "plain DC+5AC, defrag in the tuned shape");
+    check(sf_set_launch_shape(&d, 0, NULL), "sf_set_launch_shape");
+    check(sf_set_launch_shape(&d, 1, NULL), "sf_set_launch_shape");
+  }
+
   /* precision form: fp16 public values, 2-bit residual codes, exception slots */
   {
     sf_desc dl = d;
