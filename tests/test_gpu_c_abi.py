@@ -19,4 +19,4 @@ def test_c_program_round_trips(tmp_path):
     print(r.stdout, r.stderr, flush=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "c abi round trips ok" in r.stdout
-    assert r.stdout.count(": 0 of") == 5
+    assert r.stdout.count(": 0 of") == 7
