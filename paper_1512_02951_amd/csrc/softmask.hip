@@ -199,6 +199,9 @@ __global__ __launch_bounds__(kThreads) void sm_forward_kernel(SmArgs a) {
   const size_t plane = (size_t)blockIdx.y * g.H * g.W;
   float e_acc = 0.0f;   // lane n: energy of frequency n over the wave's blocks
   float sx[1] = {0.0f}; // per lane: sum of its blocks' samples
+  __shared__ f4v s_rows[kP ? kWaves : 1][128];  // per wave: one row of P for 64 blocks
+  f4v *srow = s_rows[kP ? threadIdx.x >> 6 : 0];
+  const bool rows = kP && g.Bx % 64u == 0u;   // every tile: 64 consecutive blocks of one block row
   sm_tiles(g, [&](uint32_t org, bool valid) {
     float c[64];
     load_fblock(a.x + plane, g.W, org, valid, c);
@@ -213,7 +216,25 @@ __global__ __launch_bounds__(kThreads) void sm_forward_kernel(SmArgs a) {
 #pragma unroll
       for (int n = 0; n < 64; ++n) c[n] *= keep[n];
       idct8x8(c, a.K);
-      if (valid) store_fblock(a.p_out + plane, g.W, org, c);
+      if (rows) {
+        // each row of the tile through LDS, so that one store instruction
+        // writes 1 KB of contiguous samples (32 blocks' row segments, whole
+        // cache lines) instead of every other 16 bytes of 2 KB
+        const uint32_t lane = threadIdx.x & 63u;
+        float *dst = a.p_out + plane + __builtin_amdgcn_readfirstlane(org);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const f4v lo = {c[8 * r], c[8 * r + 1], c[8 * r + 2], c[8 * r + 3]};
+          const f4v hi = {c[8 * r + 4], c[8 * r + 5], c[8 * r + 6], c[8 * r + 7]};
+          srow[2 * lane] = lo;
+          srow[2 * lane + 1] = hi;
+          const f4v v0 = srow[lane], v1 = srow[64 + lane];
+          __builtin_nontemporal_store(v0, reinterpret_cast<f4v *>(dst + (size_t)r * g.W + 4u * lane));
+          __builtin_nontemporal_store(v1, reinterpret_cast<f4v *>(dst + (size_t)r * g.W + 256u + 4u * lane));
+        }
+      } else if (valid) {
+        store_fblock(a.p_out + plane, g.W, org, c);
+      }
     }
   });
   wg_partials<kStats, 64>(e_acc, sx, a.partials, g);
