@@ -186,6 +186,19 @@ def _tile_index(nb, P, blocks, j):
     return 64 * t * P + np.asarray(j, np.int64) * nt + (blocks - 64 * t)
 
 
+def _lp_tile_index(nb, P, blocks, j):
+    """The same for the reduced-precision layout: each tile of n_t blocks is
+    two halves of m_0 = min(32, n_t) and m_1 = n_t - 32 blocks, half h laid
+    out [rank][m_h]: 64 t P + h P m_0 + j m_h + (i mod 32), h = i div 32."""
+    import numpy as np
+    blocks = np.asarray(blocks, np.int64)
+    t, i = blocks // 64, blocks % 64
+    nt = np.minimum(64, nb - 64 * t)
+    h = i // 32
+    m0 = np.minimum(32, nt)
+    return 64 * t * P + h * P * m0 + np.asarray(j, np.int64) * np.where(h == 0, m0, nt - 32) + i % 32
+
+
 def sample_public(torch, x, fr, mask, n, seed):
     """n random blocks of image x (C, H, W) on the device: their pixels and
     the stored public values of fragment fr, as host arrays."""
@@ -196,7 +209,8 @@ def sample_public(torch, x, fr, mask, n, seed):
     blocks = np.sort(np.random.default_rng(seed).choice(nb, n, replace=False))
     xb = x.view(Cc, Hh // 8, 8, Ww // 8, 8).permute(0, 1, 3, 2, 4).reshape(nb, 64)
     xb = xb[torch.from_numpy(blocks).to(x.device)].cpu().numpy()
-    idx = _tile_index(nb, npub, np.repeat(blocks, npub), np.tile(np.arange(npub), n))
+    index = _tile_index if fr.precision == "fp32" else _lp_tile_index
+    idx = index(nb, npub, np.repeat(blocks, npub), np.tile(np.arange(npub), n))
     got = fr.public[torch.from_numpy(idx).to(x.device)].float().cpu().numpy().astype(np.float64)
     return xb, got.reshape(n, npub), mask
 

@@ -47,7 +47,11 @@
  * order (private: the P = popcount(mask) private positions; public: the other
  * 64 - P positions).
  *   public fragment : float32 (SF_FP32) or fp16 / bf16 (SF_FP16 / SF_BF16)
- *                     DCT coefficients.
+ *                     DCT coefficients.  SF_FP16 / SF_BF16 split each tile
+ *                     into halves of m_0 = min(32, n_t) and m_1 = n_t - m_0
+ *                     blocks: public value j of block 64t + 32h + i (i <
+ *                     m_h) is element 64*t*P + h*P*m_0 + j*m_h + i, so each
+ *                     half's values are one contiguous run.
  *   private fragment: int16 little-endian integers q = round_half_even(
  *                     sum_p x_p * round_half_even(2^20 B[n][p]) / 2^20 ),
  *                     as one byte stream, AES-128-CTR encrypted with counter

@@ -756,22 +756,24 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
           __builtin_amdgcn_raw_buffer_store_b64(cw, res, off, 0, kNonTemporal);
         }
 
-        // ---- this half's public values, 16 bytes per lane
+        // ---- this half's public values: the half's region of the fragment
+        // ([rank][32 blocks], contiguous) leaves as 16-byte stores, whole
+        // cache lines per instruction
         wave_lds_sync();
         uint16_t *pub_tile = a.pub + b0 * npub;
         if (ntb == 64u) {
           const __amdgpu_buffer_rsrc_t prs = buffer_rsrc(pub_tile, npub * 128u);
           for (uint32_t c = (uint32_t)lane; c < 4u * npub; c += 64u) {
-            const uint32_t r = c >> 2, part = c & 3u;
-            const uint4 v = *reinterpret_cast<const uint4 *>(W.pub + 64u * r + 16u * part);
+            const uint4 v = *reinterpret_cast<const uint4 *>(W.pub + 16u * c);
             const u32x4 vv = {v.x, v.y, v.z, v.w};
-            __builtin_amdgcn_raw_buffer_store_b128(vv, prs, 128u * r + 64u * nt + 16u * part, 0, kNonTemporal);
+            __builtin_amdgcn_raw_buffer_store_b128(vv, prs, 64u * npub * nt + 16u * c, 0, kNonTemporal);
           }
         } else {
-          const uint32_t nv = ntb > 32u * nt ? min(32u, ntb - 32u * nt) : 0u;
+          const uint32_t m0 = min(32u, ntb), nv = ntb > 32u * nt ? min(32u, ntb - 32u * nt) : 0u;
           for (uint32_t c = (uint32_t)lane; c < 32u * npub; c += 64u) {
             const uint32_t r = c >> 5, j = c & 31u;
-            if (j < nv) pub_tile[r * ntb + 32u * nt + j] = *reinterpret_cast<const uint16_t *>(W.pub + 64u * r + 2u * j);
+            if (j < nv)
+              pub_tile[nt * npub * m0 + r * nv + j] = *reinterpret_cast<const uint16_t *>(W.pub + 64u * r + 2u * j);
           }
         }
         wave_lds_sync();
@@ -839,10 +841,12 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(L
           code0 = cw.x;
           code1 = cw.y;
         }
-        // ---- operands: public values straight from the fragment (tile-
-        // relative offsets: the pair's ranks are 4 apart for "DC + k AC"),
-        // private integers from the decrypted stage
-        const uint32_t vbase = 2u * jb, vbase4 = 2u * jb + 8u * ntb * h;
+        // ---- operands: public values straight from the fragment (half-
+        // relative offsets: the half's region holds [rank][m blocks], and the
+        // pair's ranks are 4 apart for "DC + k AC"), private integers from
+        // the decrypted stage
+        const uint32_t m0 = min(32u, ntb), mh = nt ? (ntb > 32u ? ntb - 32u : 0u) : m0;
+        const uint32_t vbase = 2u * (nt * npub * m0 + jl), vbase4 = vbase + 8u * mh * h;
         uint4 chi[4], clo[4];
         bool has_lo[4];
         static_for<0, 4>([&](auto sc) {
@@ -870,10 +874,10 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_defrag_kernel(L
               if (P.any_pub) {
                 uint32_t pv;
                 if constexpr (MP::kStatic)
-                  pv = P.both_pub ? __builtin_amdgcn_raw_buffer_load_b16(prs, vbase4, (int)(2u * ntb * P.c0.rank), 0)
-                                  : __builtin_amdgcn_raw_buffer_load_b16(prs, vbase, (int)(2u * ntb * P.c1.rank), 0);
+                  pv = P.both_pub ? __builtin_amdgcn_raw_buffer_load_b16(prs, vbase4, (int)(2u * mh * P.c0.rank), 0)
+                                  : __builtin_amdgcn_raw_buffer_load_b16(prs, vbase, (int)(2u * mh * P.c1.rank), 0);
                 else
-                  pv = __builtin_amdgcn_raw_buffer_load_b16(prs, vbase + 2u * ntb * P.pub_rank(h), 0, 0);
+                  pv = __builtin_amdgcn_raw_buffer_load_b16(prs, vbase + 2u * mh * P.pub_rank(h), 0, 0);
                 if (!P.mine_priv) v = pv;
               }
               w |= v << (16 * e);

@@ -70,6 +70,17 @@ def test_tile_index_matches_the_oracle_layout():
         assert np.array_equal(got, [oracle.tile_offset(nb, P, int(bb), int(jj)) for bb, jj in zip(b, j)])
 
 
+def test_reduced_precision_index_hand_example_and_permutation():
+    import numpy as np
+    # 100 blocks, P = 2: tile 0 in halves of 32 and 32 blocks, tile 1 (36 blocks) in 32 and 4
+    f = bench._lp_tile_index
+    assert [int(f(100, 2, b, j)) for b, j in ((0, 0), (31, 1), (32, 0), (33, 1), (64, 1), (96, 0), (99, 1))] == \
+        [0, 63, 64, 97, 160, 192, 199]
+    for nb, P in ((64, 54), (150, 54), (7, 3), (33, 5)):
+        idx = f(nb, P, np.arange(nb).repeat(P), np.tile(np.arange(P), nb))
+        assert np.array_equal(np.sort(idx), np.arange(nb * P))
+
+
 def test_accuracy_of_sampled_blocks_against_the_oracle(monkeypatch):
     """The cpu_baseline leg's comparison: exact public values give 0; moving
     one value of one block by d gives d / |block|_2 for that block."""

@@ -55,6 +55,36 @@ def gpu():
     assert sf.lib().sf_init() == 0, sf.lib().sf_last_error()
 
 
+def lp_public_index(nb: int, P: int, blocks, j) -> np.ndarray:
+    """Element index of public value j of block b in the reduced-precision
+    layout (C ABI): tile t = b // 64 of n_t blocks, half h = (b % 64) // 32
+    with m_0 = min(32, n_t) and m_1 = n_t - 32 blocks, each half
+    [rank][m_h blocks]: 64 t P + h P m_0 + j m_h + b % 32."""
+    b = np.asarray(blocks, np.int64)
+    j = np.asarray(j, np.int64)
+    t, i = b // 64, b % 64
+    nt = np.minimum(64, nb - 64 * t)
+    h = i // 32
+    m0 = np.minimum(32, nt)
+    mh = np.where(h == 0, m0, nt - 32)
+    return 64 * t * P + h * P * m0 + j * mh + i % 32
+
+
+def lp_public_unpack(flat: np.ndarray, nb: int, P: int) -> np.ndarray:
+    idx = lp_public_index(nb, P, np.repeat(np.arange(nb), P), np.tile(np.arange(P), nb))
+    return flat[idx].reshape(nb, P)
+
+
+def test_lp_public_index_hand_example():
+    # 100 blocks, P = 2: tile 0 halves of 32 blocks, tile 1 (36 blocks) halves of 32 and 4
+    assert lp_public_index(100, 2, 0, 0) == 0 and lp_public_index(100, 2, 31, 1) == 32 + 31
+    assert lp_public_index(100, 2, 32, 0) == 64 and lp_public_index(100, 2, 33, 1) == 64 + 32 + 1
+    assert lp_public_index(100, 2, 64, 1) == 128 + 32 and lp_public_index(100, 2, 96, 0) == 128 + 64
+    assert lp_public_index(100, 2, 99, 1) == 128 + 64 + 4 + 3
+    idx = lp_public_index(100, 2, np.repeat(np.arange(100), 2), np.tile(np.arange(2), 100))
+    assert np.array_equal(np.sort(idx), np.arange(200))
+
+
 def _public_f64(t: torch.Tensor) -> np.ndarray:
     return t.float().cpu().numpy().astype(np.float64)
 
@@ -75,7 +105,7 @@ def _check(x, mask, prec, key=None, ctr0=None, label=""):
     else:
         assert np.array_equal(got, ref["cipher"]), "ciphertext differs"
     if npub:
-        pub = oracle.tile_unpack(_public_f64(fr.public[: nb * npub]), nb, npub)
+        pub = lp_public_unpack(_public_f64(fr.public[: nb * npub]), nb, npub)
         pub_ref = oracle.tile_unpack(ref["public"], nb, npub)
         nrm = np.linalg.norm(oracle.blocks_of(x).astype(np.float64), axis=1)
         err = np.linalg.norm(pub - pub_ref, axis=1)
@@ -210,7 +240,7 @@ def test_lp_workload3_full_size(prec):
             k1 = ks[np.arange(byte.size), byte % 16 + 1]
             plain = (priv_all[byte] ^ k0).astype(np.uint16) | ((priv_all[byte + 1] ^ k1).astype(np.uint16) << 8)
             assert np.array_equal(plain.view(np.int16), ref_priv[:, j]), "private coefficient %d differs" % j
-        idx = oracle.tile_offsets(nb, npub, np.repeat(blocks, npub), np.tile(np.arange(npub), blocks.size))
+        idx = lp_public_index(nb, npub, np.repeat(blocks, npub), np.tile(np.arange(npub), blocks.size))
         got = _public_f64(pub_all[torch.from_numpy(idx).cuda()]).reshape(blocks.size, npub)
         nrm = np.linalg.norm(xb.astype(np.float64), axis=1)
         err = np.linalg.norm(got - ref_pub, axis=1)
