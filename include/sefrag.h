@@ -227,7 +227,8 @@ int sf_set_launch_shape(const sf_desc *desc, int which, const sf_launch_shape *s
 /* sf_get_launch_shape -- the shape that the next frag_image (which = 0) or
  * defrag_image (which = 1) for desc would use on the current device (the
  * stored one, else the default, resolved: waves_per_group is never 0).
- * Host only.  Returns SF_OK, or SF_EINVAL / SF_ESHAPE for bad arguments. */
+ * Host only.  Returns SF_OK, SF_EINVAL / SF_ESHAPE for bad arguments, or
+ * SF_ENOTSUP when no workgroup of this form fits the selection's LDS. */
 int sf_get_launch_shape(const sf_desc *desc, int which, sf_launch_shape *out);
 
 /* sf_tune_image -- times frag_image and then defrag_image of the image in
