@@ -470,6 +470,7 @@ def _form_batching(sf, torch, synth, dev, steps, warmup, status, out):
     out["batching"] = {"workload": "2000 images, sides log-uniform in [256, 4096], C in {1, 3}, k in {1, 2, 5, 9}, "
                                    "one persistent kernel per direction, HIP graph",
                        "tiles_per_grab": tuning[0], "workgroups_per_cu": tuning[1],
+                       "schedule": ("work queue", "static chunks")[tuning[2]],
                        "ms_per_step": round(ms, 4), "MP/s": round(samples / 1e6 / (ms * 1e-3), 1),
                        "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                        "direct_launch_ms_per_step": round(ms_direct, 4)}

@@ -271,21 +271,31 @@ typedef struct sf_batch_item {
   uint8_t ctr0[16];                 /* this image's initial counter block           */
 } sf_batch_item;
 
-/* Launch shape of a batch run: consecutive 64-block tiles a wavefront takes
- * per grab of the work queue, and workgroups (of 4 wavefronts) per compute
- * unit (0 = as many as fit).  NULL tuning = {8, 0}. */
+/* Launch shape of a batch run (workgroups of 4 wavefronts, one persistent
+ * grid) over the batch's 64-block tiles, numbered image after image.
+ * schedule 0, work queue: the run first clears a counter, then each
+ * wavefront grabs tiles_per_grab consecutive tiles per atomic add.
+ * schedule 1, static chunks: the tiles are cut into chunks of
+ * 4 * tiles_per_grab consecutive tiles dealt round-robin to the workgroups,
+ * the wavefronts of a workgroup taking every 4th tile of its chunk (faster on
+ * large line-aligned images).  tiles_per_grab 0 = the schedule's default (8
+ * queue, 2 static; at most 1024); workgroups_per_cu 0 = as many as fit.
+ * reserved must be 0.  NULL tuning = {8, 0, 0, 0}.  Every shape gives the
+ * same fragments. */
 typedef struct sf_batch_tuning {
   uint32_t tiles_per_grab;
   uint32_t workgroups_per_cu;
-  uint32_t reserved[2];
+  uint32_t schedule;
+  uint32_t reserved;
 } sf_batch_tuning;
 
 /* Device workspace bytes for a plan of n_items images. */
 size_t sf_batch_workspace_bytes(uint32_t n_items);
 
-/* Validates the items, writes their descriptors, tile counts and the AES key
- * (key = 16 host bytes, or NULL to leave private integers in clear) into
- * d_workspace, and scans the counts on the device.  Synchronises `stream`
+/* Validates the items and writes their descriptors, each image's first
+ * global tile, a table from tile ranges to the images they fall in, and the
+ * AES key (key = 16 host bytes, or NULL to leave private integers in clear)
+ * into d_workspace (one copy from the host).  Synchronises `stream`
  * before returning (the host item array may be released afterwards).  Not
  * capturable into a graph; the run calls below are.  Returns SF_OK,
  * SF_EINVAL (bad item, with its index in sf_last_error), SF_ESHAPE,
@@ -293,16 +303,19 @@ size_t sf_batch_workspace_bytes(uint32_t n_items);
 int sf_batch_plan(const sf_batch_item *items, uint32_t n_items, const uint8_t *key, void *d_workspace,
                   size_t workspace_bytes, void *stream);
 
-/* Fragment / defragment every image of the planned batch: a reset of the
- * work counter plus one persistent kernel, both on `stream`.  Returns
- * SF_EINVAL, launching nothing, when the plan has an item without the
- * direction's image buffer (d_pixels for frag, d_restored for defrag). */
+/* Fragment / defragment every image of the planned batch: one persistent
+ * kernel on `stream` (the work-queue schedule adds a reset of its counter
+ * before it).  Returns SF_EINVAL, launching nothing, for an unknown
+ * schedule, a nonzero reserved field, or a plan with an item without the
+ * direction's image buffer (d_pixels for frag, d_restored for defrag), and
+ * SF_ERANGE for tiles_per_grab above 1024. */
 int sf_frag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream);
 int sf_defrag_batch(const void *d_workspace, const sf_batch_tuning *tuning, uint32_t *d_status, void *stream);
 
-/* Autotuner: times frag + defrag of the planned batch for tiles_per_grab in
- * {1,2,4,8,16} x workgroups_per_cu in {1,2,3} (one warm pass, two timed
- * round trips each) and returns the fastest; *best_ms = its round-trip time.
+/* Autotuner: times frag + defrag of the planned batch for the work queue
+ * with tiles_per_grab in {4,8,16,32} and the static schedule with {1,2,4,8},
+ * each with workgroups_per_cu in {1,2,3} (one warm pass, two timed round
+ * trips each) and returns the fastest; *best_ms = its round-trip time.
  * Runs the batch many times (outputs are rewritten with identical values).
  * Needs both d_pixels and d_restored on every item (else SF_EINVAL, nothing
  * launched). */

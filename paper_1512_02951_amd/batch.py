@@ -2,8 +2,9 @@
 sf_batch_autotune): argument marshalling and buffer allocation with torch only.
 
 A :class:`Batch` owns the fragments of a list of images and a planned device
-workspace; :meth:`Batch.frag` / :meth:`Batch.defrag` enqueue one reset and one
-persistent kernel each and can be captured into a HIP graph.  The tuner's
+workspace; :meth:`Batch.frag` / :meth:`Batch.defrag` enqueue one persistent
+kernel each (plus a counter reset for the work-queue schedule) and can be
+captured into a HIP graph.  The tuner's
 choice can be cached in a small JSON file keyed by device and batch shape.
 """
 from __future__ import annotations
@@ -25,7 +26,10 @@ class SfBatchItem(ctypes.Structure):
 
 class SfBatchTuning(ctypes.Structure):
     _fields_ = [("tiles_per_grab", ctypes.c_uint32), ("workgroups_per_cu", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("schedule", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+SCHED_QUEUE, SCHED_STATIC = 0, 1
 
 
 def _declare(L):
@@ -99,7 +103,8 @@ class Batch:
             return None
         if isinstance(t, SfBatchTuning):
             return ctypes.byref(t)
-        return ctypes.byref(SfBatchTuning(int(t[0]), int(t[1])))
+        # (tiles_per_grab, workgroups_per_cu[, schedule])
+        return ctypes.byref(SfBatchTuning(int(t[0]), int(t[1]), int(t[2]) if len(t) > 2 else SCHED_QUEUE))
 
     def frag(self, tuning=None, status=None, stream=None):
         check(lib().sf_frag_batch(ctypes.c_void_p(self.workspace.data_ptr()), self._tuning(tuning),
@@ -116,8 +121,8 @@ class Batch:
         return "n%d_s%d_m%s" % (len(self.images), tot, hashlib.sha1(repr(mix).encode()).hexdigest()[:8])
 
     def autotune(self, cache: str | None = None, stream=None):
-        """Pick tiles_per_grab / workgroups_per_cu with the library's tuner;
-        reuse a cached choice for the same device and batch signature."""
+        """Pick (tiles_per_grab, workgroups_per_cu, schedule) with the library's
+        tuner; reuse a cached choice for the same device and batch signature."""
         import torch
         dev = torch.cuda.get_device_properties(self.workspace.device)
         key = "%s|%s" % (getattr(dev, "gcnArchName", dev.name), self.signature())
@@ -126,15 +131,16 @@ class Batch:
             with open(cache) as f:
                 table = json.load(f)
         if key in table:
-            self.tuning = (table[key]["tiles_per_grab"], table[key]["workgroups_per_cu"])
-            return self.tuning, table[key].get("ms")
+            e = table[key]
+            self.tuning = (e["tiles_per_grab"], e["workgroups_per_cu"], e.get("schedule", SCHED_QUEUE))
+            return self.tuning, e.get("ms")
         best, ms = SfBatchTuning(), ctypes.c_float()
         check(lib().sf_batch_autotune(ctypes.c_void_p(self.workspace.data_ptr()), ctypes.byref(best),
                                       ctypes.byref(ms), _stream(stream)))
-        self.tuning = (best.tiles_per_grab, best.workgroups_per_cu)
+        self.tuning = (best.tiles_per_grab, best.workgroups_per_cu, best.schedule)
         if cache:
             table[key] = {"tiles_per_grab": best.tiles_per_grab, "workgroups_per_cu": best.workgroups_per_cu,
-                          "ms": ms.value}
+                          "schedule": best.schedule, "ms": ms.value}
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)

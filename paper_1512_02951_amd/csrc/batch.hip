@@ -2,22 +2,33 @@
 // kernel per direction.
 //
 //   plan (host, once):  validate the items, write per-image descriptors,
-//                       per-image tile counts and the AES key into the
-//                       caller's device workspace; a one-workgroup device
-//                       scan (wave prefix sums) turns the counts into tile
-//                       offsets.
-//   run  (graph-safe):  a tiny kernel clears the work counter, then a
-//                       persistent grid of waves grabs `tiles_per_grab`
-//                       consecutive global tiles at a time from an atomic
-//                       queue, finds each tile's image by binary search over
-//                       the offsets, and runs the same per-tile body as the
-//                       single-image kernels (plain_tile.h) with that image's
-//                       geometry, selection, fragments and counter block.
+//                       the images' first global tiles, a bucket table that
+//                       narrows a tile's image to a few candidates, and the
+//                       AES key into the caller's device workspace.
+//   run  (graph-safe):  one persistent grid per direction runs the same
+//                       per-tile body as the single-image kernels
+//                       (plain_tile.h) on every global tile, with the
+//                       geometry, selection, fragments and counter block of
+//                       the tile's image.  Two schedules:
+//                       work queue (default): a kernel clears a counter,
+//                       then each wave grabs tiles_per_grab consecutive
+//                       tiles per atomic.
+//                       static chunks: the global tiles are cut
+//                       into chunks of 4 * tiles_per_grab consecutive tiles,
+//                       dealt round-robin to the workgroups, the 4 waves of
+//                       a workgroup taking interleaved tiles of its chunk.
+//                       The tiles in flight form one dense window, as in the
+//                       single-image kernels.  Faster on large line-aligned
+//                       images (the queue's waves work through their grabs
+//                       one tile after another, so the tiles in flight are
+//                       spread out), slower on the batching workload's many
+//                       unaligned ones.
 //
-// The tuner times candidate (tiles_per_grab, workgroups per CU) pairs on the
-// planned batch and reports the fastest.
+// The tuner times candidate (schedule, tiles_per_grab, workgroups per CU)
+// triples on the planned batch and reports the fastest.
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -45,53 +56,34 @@ struct BatchHeader {
   uint32_t enc;          // AES enabled
   uint32_t total_tiles;  // filled by the scan
   uint32_t max_npriv;
-  uint32_t queue[4];     // work counters (frag, defrag)
+  uint32_t queue[4];     // work counters of the queue schedule (frag, defrag)
+  uint32_t bucket_shift; // tile t lies in image buckets[t >> bucket_shift] ..
+  uint32_t nbuckets;     //   buckets[(t >> bucket_shift) + 1]
+  uint32_t pad[2];
   AesKey key;
 };
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15u) & ~(size_t)15u; }
 
+// Bucket table entries (+1): 16 per image rounded up to a power of two, at
+// least 1024 and at most 2^22, so that a bucket holds a few images at most
+// unless the images' tile counts are very uneven.
+__host__ __device__ inline uint32_t bucket_count(uint32_t n) {
+  uint64_t want = 16ull * n, nb = 1024;
+  while (nb < want && nb < (1ull << 22)) nb <<= 1;
+  return (uint32_t)nb;
+}
+
 struct WsLayout {
-  size_t desc, counts, offsets, total;
+  size_t desc, offsets, buckets, total;
 };
 __host__ __device__ inline WsLayout ws_layout(uint32_t n) {
   WsLayout L;
   L.desc = align16(sizeof(BatchHeader));
-  L.counts = L.desc + align16(sizeof(BatchDesc) * (size_t)n);
-  L.offsets = L.counts + align16(4u * (size_t)n);
-  L.total = L.offsets + align16(4u * ((size_t)n + 1u));
+  L.offsets = L.desc + align16(sizeof(BatchDesc) * (size_t)n);
+  L.buckets = L.offsets + align16(4u * ((size_t)n + 1u));
+  L.total = L.buckets + align16(4u * ((size_t)bucket_count(n) + 1u));
   return L;
-}
-
-// Exclusive scan of n tile counts -> n + 1 offsets (offsets[n] = total), one
-// workgroup of 1024 threads, chunks of 1024 with a running carry.
-__global__ __launch_bounds__(1024) void batch_scan_kernel(uint8_t *ws, uint32_t n) {
-  const WsLayout L = ws_layout(n);
-  const uint32_t *counts = reinterpret_cast<const uint32_t *>(ws + L.counts);
-  uint32_t *offs = reinterpret_cast<uint32_t *>(ws + L.offsets);
-  __shared__ uint32_t wave_sums[16];
-  __shared__ uint32_t carry;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < n; base += 1024) {
-    const uint32_t i = base + tid;
-    const uint32_t v = i < n ? counts[i] : 0u;
-    uint32_t wtotal;
-    const uint32_t excl = wave_exclusive_scan(v, lane, wtotal);
-    if (lane == 0) wave_sums[wave] = wtotal;
-    __syncthreads();
-    uint32_t before = carry;
-    for (int w = 0; w < wave; ++w) before += wave_sums[w];
-    if (i < n) offs[i] = before + excl;
-    __syncthreads();
-    if (tid == 1023) carry = before + excl + v;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    offs[n] = carry;
-    reinterpret_cast<BatchHeader *>(ws)->total_tiles = carry;
-  }
 }
 
 __global__ void batch_reset_kernel(uint8_t *ws, int which) { reinterpret_cast<BatchHeader *>(ws)->queue[which] = 0u; }
@@ -110,9 +102,12 @@ __device__ __forceinline__ BatchDesc load_desc(const BatchDesc *p) {
   return d;
 }
 
-// Image holding global tile gt: the last i with offsets[i] <= gt.
-__device__ __forceinline__ uint32_t find_image(const uint32_t *offs, uint32_t n, uint32_t gt) {
-  uint32_t lo = 0, hi = n;  // offs[lo] <= gt < offs[hi]
+// Image holding global tile gt: the last i with offsets[i] <= gt, searched
+// between the bounds that gt's bucket gives.
+__device__ __forceinline__ uint32_t find_image(const uint32_t *offs, const uint32_t *bk, uint32_t shift,
+                                               uint32_t gt) {
+  const uint32_t b = gt >> shift;
+  uint32_t lo = bk[b], hi = bk[b + 1] + 1u;  // offs[lo] <= gt < offs[hi]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (offs[mid] <= gt) lo = mid;
@@ -121,27 +116,46 @@ __device__ __forceinline__ uint32_t find_image(const uint32_t *offs, uint32_t n,
   return lo;
 }
 
-// Runs body(tile, desc) for every tile of the batch, grabbing
-// tiles_per_grab consecutive tiles per atomic.
-template <class Body>
+constexpr int kSchedQueue = 0, kSchedStatic = 1;
+constexpr uint32_t kDefaultChunkTiles = 2;
+
+// Runs body(tile, desc) for every tile of the batch, in the schedule kSched
+// (see the top of this file).
+template <int kSched, class Body>
 __device__ __forceinline__ void batch_loop(uint8_t *ws, uint32_t n, int which, uint32_t tiles_per_grab, int lane,
                                            Body &&body) {
   const WsLayout L = ws_layout(n);
   BatchHeader *hd = reinterpret_cast<BatchHeader *>(ws);
   const BatchDesc *descs = reinterpret_cast<const BatchDesc *>(ws + L.desc);
   const uint32_t *offs = reinterpret_cast<const uint32_t *>(ws + L.offsets);
-  const uint32_t total = hd->total_tiles;
-  for (;;) {
-    uint32_t w = 0;
-    if (lane == 0) w = atomicAdd(&hd->queue[which], tiles_per_grab);
-    w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
-    if (w >= total) break;
-    const uint32_t end = min(w + tiles_per_grab, total);
-    uint32_t img = find_image(offs, n, w);
-    for (uint32_t gt = w; gt < end; ++gt) {
-      while (offs[img + 1] <= gt) ++img;
-      img = __builtin_amdgcn_readfirstlane(img);
-      body(gt - offs[img], load_desc(descs + img));
+  const uint32_t *bk = reinterpret_cast<const uint32_t *>(ws + L.buckets);
+  const uint32_t total = hd->total_tiles, shift = hd->bucket_shift;
+  if (kSched == kSchedStatic) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t G = gridDim.x, chunk = kWaves * tiles_per_grab;
+    const uint32_t nchunks = (uint32_t)(((uint64_t)total + chunk - 1) / chunk);
+    for (uint32_t c = blockIdx.x; c < nchunks; c += G) {
+      const uint32_t base = c * chunk, end = base + min(chunk, total - base);
+      uint32_t img = __builtin_amdgcn_readfirstlane(find_image(offs, bk, shift, base));
+      for (uint32_t gt = base + wave; gt < end; gt += kWaves) {
+        while (offs[img + 1] <= gt) ++img;
+        img = __builtin_amdgcn_readfirstlane(img);
+        body(gt - offs[img], load_desc(descs + img));
+      }
+    }
+  } else {
+    for (;;) {
+      uint32_t w = 0;
+      if (lane == 0) w = atomicAdd(&hd->queue[which], tiles_per_grab);
+      w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
+      if (w >= total) break;
+      const uint32_t end = min(w + tiles_per_grab, total);
+      uint32_t img = __builtin_amdgcn_readfirstlane(find_image(offs, bk, shift, w));
+      for (uint32_t gt = w; gt < end; ++gt) {
+        while (offs[img + 1] <= gt) ++img;
+        img = __builtin_amdgcn_readfirstlane(img);
+        body(gt - offs[img], load_desc(descs + img));
+      }
     }
   }
 }
@@ -174,6 +188,7 @@ __device__ __forceinline__ void dispatch_mask(uint64_t mask, F &&f) {
 // when the wave moves to an image with another mask).
 constexpr uint32_t kBatchQ2Bytes = kQ2StageBytes + 64u * sizeof(Q2Operands);
 
+template <int kSched>
 __global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
@@ -189,7 +204,7 @@ __global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
   uint64_t qmask = 0;  // mask whose operands wq holds (masks are never 0)
   // the body must be inlined: its buffer resources and table pointers live in
   // scalar registers, which an outlined call could not guarantee
-  batch_loop(a.ws, a.n, 0, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) __attribute__((always_inline)) {
+  batch_loop<kSched>(a.ws, a.n, 0, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) __attribute__((always_inline)) {
     FragOut o;
     o.pub = d.pub;
     o.priv = d.priv;
@@ -218,6 +233,7 @@ __global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
   });
 }
 
+template <int kSched>
 __global__ __launch_bounds__(kThreads, 3) void defrag_batch_kernel(BatchArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
@@ -228,7 +244,7 @@ __global__ __launch_bounds__(kThreads, 3) void defrag_batch_kernel(BatchArgs a) 
   if (enc) aes_load_tables(s_aes, a.aes_t0, hd->key, threadIdx.x, kThreads);
   __syncthreads();
   uint8_t *lp = s_dyn + wave * a.lds_priv_bytes;
-  batch_loop(a.ws, a.n, 1, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) __attribute__((always_inline)) {
+  batch_loop<kSched>(a.ws, a.n, 1, a.tiles_per_grab, lane, [&](uint32_t t, const BatchDesc &d) __attribute__((always_inline)) {
     DefragIn in;
     in.pix_out = d.out;
     in.pub = d.pub;
@@ -267,9 +283,12 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   BatchArgs a;
   a.ws = (uint8_t *)p.ws;
   a.n = p.n;
-  // default: the grab the tuner picks on the batching workload (8 tiles;
-  // larger grabs keep the lines shared by neighbouring tiles on one wave)
-  a.tiles_per_grab = tuning && tuning->tiles_per_grab ? tuning->tiles_per_grab : 8u;
+  const uint32_t sched = tuning ? tuning->schedule : (uint32_t)kSchedQueue;
+  if ((sched != (uint32_t)kSchedStatic && sched != (uint32_t)kSchedQueue) || (tuning && tuning->reserved))
+    return fail(SF_EINVAL, "schedule must be 0 (work queue) or 1 (static chunks), reserved 0");
+  // defaults: what the tuner picks on the batching workload
+  a.tiles_per_grab = tuning && tuning->tiles_per_grab ? tuning->tiles_per_grab
+                                                      : (sched == (uint32_t)kSchedStatic ? kDefaultChunkTiles : 8u);
   a.lds_priv_bytes = (2u * p.max_npriv * 64u + 15u) & ~15u;
   a.status = status;
   a.aes_t0 = ds.d_aes_t0;
@@ -278,7 +297,9 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   a.K = host_tables().dct;
   if (a.tiles_per_grab > 1024) return fail(SF_ERANGE, "tiles_per_grab must be at most 1024");
   const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + (which == 0 ? kBatchQ2Bytes : 0u));
-  const void *fn = which == 0 ? (const void *)frag_batch_kernel : (const void *)defrag_batch_kernel;
+  const bool st = sched == (uint32_t)kSchedStatic;
+  const void *fn = which == 0 ? (st ? (const void *)frag_batch_kernel<kSchedStatic> : (const void *)frag_batch_kernel<kSchedQueue>)
+                              : (st ? (const void *)defrag_batch_kernel<kSchedStatic> : (const void *)defrag_batch_kernel<kSchedQueue>);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   if (tuning && tuning->workgroups_per_cu) per_cu = tuning->workgroups_per_cu < (uint32_t)per_cu ? (int)tuning->workgroups_per_cu : per_cu;
@@ -286,11 +307,15 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   uint64_t grid = (uint64_t)ds.num_cu * (uint64_t)per_cu;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.ws, which);
-  if (which == 0)
-    hipLaunchKernelGGL(frag_batch_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+  if (!st) hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.ws, which);
+  if (which == 0 && st)
+    hipLaunchKernelGGL(frag_batch_kernel<kSchedStatic>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+  else if (which == 0)
+    hipLaunchKernelGGL(frag_batch_kernel<kSchedQueue>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+  else if (st)
+    hipLaunchKernelGGL(defrag_batch_kernel<kSchedStatic>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
   else
-    hipLaunchKernelGGL(defrag_batch_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(defrag_batch_kernel<kSchedQueue>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "batch kernel launch");
 }
@@ -307,7 +332,8 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
   std::vector<uint8_t> host(L.total, 0);
   BatchHeader *hd = reinterpret_cast<BatchHeader *>(host.data());
   BatchDesc *descs = reinterpret_cast<BatchDesc *>(host.data() + L.desc);
-  uint32_t *counts = reinterpret_cast<uint32_t *>(host.data() + L.counts);
+  uint32_t *offs = reinterpret_cast<uint32_t *>(host.data() + L.offsets);
+  uint32_t *bk = reinterpret_cast<uint32_t *>(host.data() + L.buckets);
   hd->n = n;
   hd->enc = key ? 1u : 0u;
   if (key) aes_expand_key(key, hd->key.rk);
@@ -349,16 +375,29 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
     for (int b = 8; b < 16; ++b) lo = (lo << 8) | it.ctr0[b];
     bd.ctr_hi = hi;
     bd.ctr_lo = lo;
-    counts[i] = g.ntiles;
+    offs[i] = (uint32_t)total;
     total += g.ntiles;
+    if (total >= (1ull << 31)) return fail(SF_ERANGE, "batch holds too many tiles");
     if (g.npriv > max_npriv) max_npriv = g.npriv;
   }
-  if (total >= (1ull << 32)) return fail(SF_ERANGE, "batch holds too many tiles");
+  offs[n] = (uint32_t)total;
+  hd->total_tiles = (uint32_t)total;
   hd->max_npriv = max_npriv;
+  // bucket b covers tiles [b << shift, (b + 1) << shift); bk[b] is the image
+  // of its first tile (of the last tile for buckets past the end), so a
+  // tile of bucket b lies in one of the images bk[b] .. bk[b + 1]
+  const uint32_t nb = bucket_count(n);
+  uint32_t shift = 0;
+  while (((total - 1) >> shift) >= nb) ++shift;
+  hd->bucket_shift = shift;
+  hd->nbuckets = nb;
+  for (uint32_t b = 0, img = 0; b <= nb; ++b) {
+    const uint64_t t = std::min<uint64_t>((uint64_t)b << shift, total - 1);
+    while (offs[img + 1] <= t) ++img;
+    bk[b] = img;
+  }
   hipError_t e = hipMemcpyAsync(d_ws, host.data(), L.total, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch plan)");
-  hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(1024), 0, stream, (uint8_t *)d_ws, n);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch scan launch");
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize(batch plan)");
   PlanInfo p;
   p.ws = d_ws;
@@ -396,13 +435,16 @@ int batch_autotune(const DeviceState &ds, const void *d_ws, sf_batch_tuning *bes
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SF_EHIP, "hipEventCreate failed");
-  static const uint32_t grabs[] = {1, 2, 4, 8, 16};
+  // tiles per grab (queue; single-tile grabs wait on the one counter's
+  // atomics) or per wave and chunk (static)
+  static const uint32_t grabs[2][4] = {{4, 8, 16, 32}, {1, 2, 4, 8}};
   float best_t = 1e30f;
-  sf_batch_tuning best_c{2, 0, {0, 0}};
+  sf_batch_tuning best_c{8, 0, (uint32_t)kSchedQueue, 0};
   int rc = SF_OK;
+  for (uint32_t sched = 0; sched < 2 && rc == SF_OK; ++sched)
   for (uint32_t wpc = 1; wpc <= 3 && rc == SF_OK; ++wpc)
-    for (uint32_t gi = 0; gi < sizeof(grabs) / sizeof(grabs[0]) && rc == SF_OK; ++gi) {
-      sf_batch_tuning c{grabs[gi], wpc, {0, 0}};
+    for (uint32_t gi = 0; gi < 4 && rc == SF_OK; ++gi) {
+      sf_batch_tuning c{grabs[sched][gi], wpc, sched, 0};
       // one untimed pass, then two timed round trips
       for (int w = 0; w < 1 && rc == SF_OK; ++w) {
         rc = launch_batch(ds, p, 0, &c, nullptr, stream);

@@ -44,8 +44,11 @@ def _check_against_single(b, imgs, masks, ctrs, key):
                                            sf.DEFAULT_PER_TILE, (C, H, W)), None, (C, H, W), m, "fp32")
         sf.frag_image(x, m, key, c0, out=fr)
         torch.cuda.synchronize()
-        assert torch.equal(fr.private, b.privates[i]), "image %d private differs" % i
-        assert torch.equal(fr.public.view(torch.int32), b.publics[i].view(torch.int32)), "image %d public" % i
+        # the buffers are padded to at least 16 bytes; compare the fragments' bytes
+        pb, qb, _ = sf.fragment_sizes(H, W, C, m)
+        assert torch.equal(fr.private[:qb], b.privates[i][:qb]), "image %d private differs" % i
+        assert torch.equal(fr.public.view(torch.int32)[: pb // 4],
+                           b.publics[i].view(torch.int32)[: pb // 4]), "image %d public" % i
         if b.excs[i] is not None:
             ea = sf.ExceptionList(b.excs[i], sf.DEFAULT_PER_TILE, (C, H, W)).decode()
             eb = fr.exceptions.decode()
@@ -70,7 +73,9 @@ def test_mixed_batch_matches_single_image_path_and_oracle():
         assert np.array_equal(b.privates[i].cpu().numpy()[: ref["cipher"].size], ref["cipher"])
 
 
-@pytest.mark.parametrize("tuning", [(1, 1), (4, 2), (16, 0), (1024, 3)])
+# (tiles_per_grab, workgroups_per_cu[, schedule]): work queue, then static chunks
+@pytest.mark.parametrize("tuning", [(1, 1), (4, 2), (16, 0), (1024, 3),
+                                    (1, 1, 1), (2, 3, 1), (8, 0, 1), (1024, 2, 1)])
 def test_tunings_give_identical_results(tuning):
     imgs, masks, ctrs = _mixed(12, 5)
     key = synth.aes_key(4)
@@ -86,7 +91,8 @@ def test_graph_replays_and_autotune(tmp_path):
     key = synth.aes_key(4)
     b = Batch(imgs, masks, key, ctrs)
     tuning, ms = b.autotune(cache=str(tmp_path / "tune.json"))
-    assert tuning[0] in (1, 2, 4, 8, 16) and 1 <= tuning[1] <= 3 and ms > 0
+    assert tuning[2] in (0, 1) and 1 <= tuning[1] <= 3 and ms > 0
+    assert tuning[0] in ((4, 8, 16, 32), (1, 2, 4, 8))[tuning[2]]
     assert b.autotune(cache=str(tmp_path / "tune.json"))[0] == tuning  # cached
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
@@ -105,6 +111,38 @@ def test_graph_replays_and_autotune(tmp_path):
         g.replay()
         torch.cuda.synchronize()
         _check_against_single(b, imgs, masks, ctrs, key)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_uneven_batch(schedule):
+    """Many one-tile images around one of 12288 tiles: the tile-to-image table's
+    buckets (16 tiles each here) hold up to 16 images, searched in the kernel."""
+    imgs = [synth.image(8, 8 * (1 + i % 3), 1, 4, 2000 + i).cuda() for i in range(40)]
+    imgs.append(synth.image(4096, 4096, 3, 4, 2040).cuda())
+    imgs += [synth.image(8, 16, 1, 4, 2041 + i).cuda() for i in range(23)]
+    masks = [sf.prefix_mask((1, 2, 5, 9)[i % 4]) for i in range(len(imgs))]
+    ctrs = [synth.ctr0(4, 2000 + i) for i in range(len(imgs))]
+    key = synth.aes_key(4)
+    b = Batch(imgs, masks, key, ctrs)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.frag((1, 0, schedule), status=status)
+    b.defrag((1, 0, schedule), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    _check_against_single(b, imgs, masks, ctrs, key)
+
+
+def test_batch_run_rejects_unknown_schedules():
+    import ctypes
+    from paper_1512_02951_amd import batch as sb
+    b = Batch([synth.image(16, 24, 1, 4, 0, device="cuda")], [sf.prefix_mask(2)], None, [bytes(16)])
+    L = sb.lib()
+    ws = ctypes.c_void_p(b.workspace.data_ptr())
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for t in (sb.SfBatchTuning(8, 0, 2, 0), sb.SfBatchTuning(8, 0, 0, 1)):
+        assert L.sf_frag_batch(ws, ctypes.byref(t), None, stream) == sf.SF_EINVAL
+    assert L.sf_defrag_batch(ws, ctypes.byref(sb.SfBatchTuning(2000, 0, 1, 0)), None, stream) == sf.SF_ERANGE
+    torch.cuda.synchronize()
 
 
 def test_batch_plan_rejects_bad_items():
