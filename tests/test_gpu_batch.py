@@ -234,3 +234,17 @@ def test_workload4_2000_images():
         err = np.linalg.norm(got - ref_pub, axis=1)
         assert np.all(err[nrm == 0] == 0)
         assert (err[nrm > 0] / nrm[nrm > 0]).max() <= 1e-5
+    # the static-chunk schedule on the same plan: the same fragments (checked
+    # on the sampled images, bit for bit) and every round trip exact
+    keep = {i: (b.publics[i].clone(), b.privates[i].clone()) for i in chosen}
+    for r in b.restored:
+        r.zero_()
+    b.frag((2, 0, 1), status=status)
+    b.defrag((2, 0, 1), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    for i, (pub, prv) in keep.items():
+        assert torch.equal(pub.view(torch.int32), b.publics[i].view(torch.int32)), "image %d public (static)" % i
+        assert torch.equal(prv, b.privates[i]), "image %d private (static)" % i
+    for i, x in enumerate(imgs):
+        assert torch.equal(b.restored[i], x), "image %d round trip (static)" % i
