@@ -348,7 +348,9 @@ __device__ __forceinline__ void group_ctr_tail(const TileGroup &G, const WaveLds
                                                uint32_t npriv, int lane, const AesLds &s_aes, const AesArgs &aes,
                                                uint32_t first, uint32_t n0, uint32_t total) {
   constexpr uint32_t WB = 16u / LPB;
-  const uint32_t a = first + (uint32_t)lane / LPB, part = (uint32_t)lane % LPB;
+  (void)lane;
+  const uint32_t ln = fresh_lane();
+  const uint32_t a = first + ln / LPB, part = ln % LPB;
   const bool live = a < total;
   const bool second = a >= n0;
   const uint32_t i = second ? a - n0 : a;
@@ -437,7 +439,7 @@ __device__ __forceinline__ void load_rows(const TileGeom &g, __amdgpu_buffer_rsr
                                           int lane, uint32_t (&xr)[8]) {
   const uint64_t b = (uint64_t)t * 64u + 32u * nt + ((uint32_t)lane & 31u);
   const bool valid = b < g.nb;
-  const uint32_t voff = valid ? block_origin(g, (uint32_t)b) + 4u * ((uint32_t)lane >> 5) : 0u;
+  const uint32_t voff = valid ? block_origin(g, (uint32_t)b) + 4u * (fresh_lane() >> 5) : 0u;
 #pragma unroll
   for (int r = 0; r < 8; ++r)
     xr[r] = valid ? __builtin_amdgcn_raw_buffer_load_b32(img, voff, (int)(r * g.W), kNonTemporal) : 0u;
@@ -533,10 +535,11 @@ struct Pair {
 // encryption; unpack: after decryption), in place, one rank at a time in the
 // order that never overwrites a value still to be moved.
 template <bool kPack>
-__device__ __forceinline__ void stage_repack(uint8_t *stage, uint32_t npriv, uint32_t ntb, int lane) {
+__device__ __forceinline__ void stage_repack(uint8_t *stage, uint32_t npriv, uint32_t ntb, int) {
+  const uint32_t lane = fresh_lane();
   for (uint32_t k = 1; k < npriv; ++k) {
     const uint32_t r = kPack ? k : npriv - k;
-    const bool mine = (uint32_t)lane < ntb;
+    const bool mine = lane < ntb;
     const uint32_t from = kPack ? 128u * r : 2u * r * ntb, to = kPack ? 2u * r * ntb : 128u * r;
     const int16_t v = mine ? *reinterpret_cast<const int16_t *>(stage + from + 2u * lane) : (int16_t)0;
     wave_lds_sync();
@@ -582,7 +585,6 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
   const uint32_t npriv = g.npriv, npub = g.npub;
   const __amdgpu_buffer_rsrc_t img = buffer_rsrc(g.pix, (uint32_t)(g.nb * 64u));
   const __amdgpu_buffer_rsrc_t res = buffer_rsrc(a.resid, (uint32_t)(g.nb * 16u));
-  uint32_t flags = 0;
 
   uint32_t t = blockIdx.x * nw + wave;
   uint32_t xn[8];  // the next half's pixel rows, in flight during the current half
@@ -779,14 +781,13 @@ __global__ __launch_bounds__(512, lp_waves_per_eu<BF>()) void lp_frag_kernel(LpA
         wave_lds_sync();
       }
       if (lane == 0) a.exc.count[t] = (uint16_t)min(tile_exc, 0xffffu);
-      if (tile_exc > a.exc.per_tile) flags |= SF_STATUS_EXC_OVERFLOW;
+      if (tile_exc > a.exc.per_tile && lane == 0 && a.status) atomicOr(a.status, SF_STATUS_EXC_OVERFLOW);
       if (ntb < 64u) stage_repack<true>(stage, npriv, ntb, lane);
     }
     // ---- the group's private bytes: AES-CTR and coalesced stores
     group_ctr<true>(G, W, a.pstride, a.priv, npriv, lane, s_aes, a.aes);
     wave_lds_sync();
   }
-  if (flags && lane == 0 && a.status) atomicOr(a.status, flags);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,11 +27,38 @@
 
 namespace sf {
 
+// Unsigned division by an invariant divisor d >= 1 as a multiply-high and
+// shifts (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Sec. 4): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1 (which fits 32 bits), every 32-bit n has
+// n / d = (t + ((n - t) >> s1)) >> s2, t = mulhi(m, n), s1 = min(l, 1),
+// s2 = max(l - 1, 0).  The three words are wave-uniform kernel arguments, so
+// no vector register holds a reciprocal.
+struct UDiv {
+  uint32_t m, s1, s2;
+};
+
+inline UDiv udiv_magic(uint32_t d) {
+  uint32_t l = 0;
+  while (l < 32u && (1ull << l) < (uint64_t)d) ++l;
+  UDiv u;
+  u.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1u);
+  u.s1 = l ? 1u : 0u;
+  u.s2 = l ? l - 1u : 0u;
+  return u;
+}
+
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u) {
+  const uint32_t t = __umulhi(u.m, n);
+  return (t + ((n - t) >> u.s1)) >> u.s2;
+}
+
 struct TileGeom {
   const uint8_t *pix;
   uint32_t H, W, Bx, By;
   uint64_t nb;
   uint32_t ntiles, npriv, npub;
+  UDiv div_plane, div_bx;  // division by Bx * By and by Bx
   uint64_t mask;
 };
 
@@ -47,6 +74,8 @@ inline TileGeom tile_geom(const Geom &g, const uint8_t *pix) {
   t.npriv = g.npriv;
   t.npub = g.npub;
   t.mask = g.mask;
+  t.div_plane = udiv_magic(g.Bx * g.By);
+  t.div_bx = udiv_magic(g.Bx);
   return t;
 }
 
@@ -133,21 +162,22 @@ __device__ __forceinline__ void for_each_coef(uint64_t mask, FP &&fpriv, FQ &&fp
 
 // Sample offset of row 0 of block b within the image.
 __device__ __forceinline__ uint32_t block_origin(const TileGeom &g, uint32_t b) {
-  const uint32_t per_plane = g.Bx * g.By;
-  const uint32_t c = b / per_plane, rem = b - c * per_plane;
-  const uint32_t by = rem / g.Bx, bx = rem - by * g.Bx;
+  const uint32_t c = udiv(b, g.div_plane), rem = b - c * (g.Bx * g.By);
+  const uint32_t by = udiv(rem, g.div_bx), bx = rem - by * g.Bx;
   return c * g.H * g.W + by * 8u * g.W + bx * 8u;
 }
 
-// Exclusive prefix sum over the 64 lanes of a wave (and the total).
-__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, int lane, uint32_t &total) {
+// Exclusive prefix sum over the 64 lanes of a wave (and the total).  Called
+// by the whole wave.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, int, uint32_t &total) {
+  const uint32_t lane = fresh_lane();
   uint32_t incl = v;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(incl, d, 64);
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t o = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((lane - d) << 2), (int)incl);
     if (lane >= d) incl += o;
   }
-  total = __shfl(incl, 63, 64);
+  total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   return incl - v;
 }
 
@@ -302,7 +332,8 @@ __device__ __forceinline__ void tile_ctr_store(uint8_t *lp, uint8_t *gp, uint32_
     }
   }
   if (nrow != nblk) {
-    const uint32_t i = nrow + ((uint32_t)lane >> 2), c = (uint32_t)lane & 3u, o = 16u * i + 4u * c;
+    const uint32_t ln = fresh_lane();
+    const uint32_t i = nrow + (ln >> 2), c = ln & 3u, o = 16u * i + 4u * c;
     uint32_t v = 0u;
     if (i < nblk) v = *reinterpret_cast<const uint32_t *>(lp + o);
     v ^= ctr_word_quad(s_aes, ctr_hi, ctr_lo, ctr_first + i, c);  // every lane: quad permutes
@@ -342,7 +373,8 @@ __device__ __forceinline__ void tile_ctr_load(uint8_t *lp, const uint8_t *gp, ui
     *reinterpret_cast<uint4 *>(lp + 16u * i) = v;
   }
   if (nrow != nblk) {
-    const uint32_t i = nrow + ((uint32_t)lane >> 2), c = (uint32_t)lane & 3u, o = 16u * i + 4u * c;
+    const uint32_t ln = fresh_lane();
+    const uint32_t i = nrow + (ln >> 2), c = ln & 3u, o = 16u * i + 4u * c;
     uint32_t v = 0u;
     if (o + 4u <= tbytes) {
       v = *reinterpret_cast<const uint32_t *>(gp + o);

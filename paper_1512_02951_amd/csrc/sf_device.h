@@ -201,6 +201,15 @@ __device__ __forceinline__ void aes_load_tables(AesLds &L, const uint32_t *__res
   for (int i = tid; i < 44; i += nthreads) L.rk[i] = K.rk[i];
 }
 
+// The lane index from an opaque instruction pair: values derived from it are
+// computed where they are used rather than held (or spilled) across a whole
+// kernel from its entry.
+__device__ __forceinline__ uint32_t fresh_lane() {
+  uint32_t l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
+}
+
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // truth table of a ^ b ^ c
 }
