@@ -172,14 +172,23 @@ struct BatchArgs {
   DctK K;
 };
 
-template <class F>
+// Selections with a compiled body; kAny adds the run-time body for any other
+// mask (the plan picks the kernels without it when no image needs it: that
+// body's registers would otherwise size every tile's).
+__host__ __device__ constexpr bool compiled_mask(uint64_t mask) {
+  return mask == (1ull << 2) - 1 || mask == (1ull << 3) - 1 || mask == (1ull << 6) - 1 || mask == (1ull << 10) - 1;
+}
+
+template <bool kAny, class F>
 __device__ __forceinline__ void dispatch_mask(uint64_t mask, F &&f) {
   switch (mask) {
     case (1ull << 2) - 1: f(MaskPrefix<2>{}); break;
     case (1ull << 3) - 1: f(MaskPrefix<3>{}); break;
     case (1ull << 6) - 1: f(MaskPrefix<6>{}); break;
     case (1ull << 10) - 1: f(MaskPrefix<10>{}); break;
-    default: f(MaskRuntime{}); break;
+    default:
+      if constexpr (kAny) f(MaskRuntime{});
+      break;
   }
 }
 
@@ -188,7 +197,7 @@ __device__ __forceinline__ void dispatch_mask(uint64_t mask, F &&f) {
 // when the wave moves to an image with another mask).
 constexpr uint32_t kBatchQ2Bytes = kQ2StageBytes + 64u * sizeof(Q2Operands);
 
-template <int kSched>
+template <int kSched, bool kAny>
 __global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
@@ -215,8 +224,9 @@ __global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
     const TileLane L = tile_lane(d.g, t, lane);
     uint32_t xs[16];
     load_block(d.g, L, xs);
-    const bool mfma_q2 = __builtin_popcountll(d.g.mask & ~1ull) <= kQ2MfmaMaxAc;
-    dispatch_mask(d.g.mask, [&](auto mp) __attribute__((always_inline)) {
+    // the compiled selections have at most 9 private AC coefficients
+    const bool mfma_q2 = !kAny || __builtin_popcountll(d.g.mask & ~1ull) <= kQ2MfmaMaxAc;
+    dispatch_mask<kAny>(d.g.mask, [&](auto mp) __attribute__((always_inline)) {
       using MP = decltype(mp);
       if (mfma_q2) {
         if (d.g.mask != qmask) {
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(kThreads, 3) void frag_batch_kernel(BatchArgs a) {
   });
 }
 
-template <int kSched>
+template <int kSched, bool kAny>
 __global__ __launch_bounds__(kThreads, 3) void defrag_batch_kernel(BatchArgs a) {
   __shared__ AesLds s_aes;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_dyn[];
@@ -251,7 +261,7 @@ __global__ __launch_bounds__(kThreads, 3) void defrag_batch_kernel(BatchArgs a) 
     in.priv = d.priv;
     in.exc = d.exc;
     const TileLane L = tile_lane(d.g, t, lane);
-    dispatch_mask(d.g.mask, [&](auto mp) __attribute__((always_inline)) {
+    dispatch_mask<kAny>(d.g.mask, [&](auto mp) __attribute__((always_inline)) {
       defrag_tile<decltype(mp)>(d.g, in, t, L, lane, lp, s_aes, enc, d.ctr_hi, d.ctr_lo, a.K);
     });
   });
@@ -264,6 +274,7 @@ struct PlanInfo {
   uint64_t total_tiles = 0;
   bool all_pixels = true;    // every item has d_pixels: frag can run
   bool all_restored = true;  // every item has d_restored: defrag can run
+  bool any_mask = false;     // some item's selection has no compiled body
 };
 std::vector<PlanInfo> g_plans;  // guarded by g_plan_mu
 std::mutex g_plan_mu;
@@ -297,9 +308,16 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   a.K = host_tables().dct;
   if (a.tiles_per_grab > 1024) return fail(SF_ERANGE, "tiles_per_grab must be at most 1024");
   const size_t lds = (size_t)kWaves * (a.lds_priv_bytes + (which == 0 ? kBatchQ2Bytes : 0u));
+  // kernels by [direction][schedule][any mask]
+  using Kern = void (*)(BatchArgs);
+  static const Kern kerns[2][2][2] = {
+      {{frag_batch_kernel<kSchedQueue, false>, frag_batch_kernel<kSchedQueue, true>},
+       {frag_batch_kernel<kSchedStatic, false>, frag_batch_kernel<kSchedStatic, true>}},
+      {{defrag_batch_kernel<kSchedQueue, false>, defrag_batch_kernel<kSchedQueue, true>},
+       {defrag_batch_kernel<kSchedStatic, false>, defrag_batch_kernel<kSchedStatic, true>}}};
   const bool st = sched == (uint32_t)kSchedStatic;
-  const void *fn = which == 0 ? (st ? (const void *)frag_batch_kernel<kSchedStatic> : (const void *)frag_batch_kernel<kSchedQueue>)
-                              : (st ? (const void *)defrag_batch_kernel<kSchedStatic> : (const void *)defrag_batch_kernel<kSchedQueue>);
+  const Kern kern = kerns[which][st ? 1 : 0][p.any_mask ? 1 : 0];
+  const void *fn = (const void *)kern;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   if (tuning && tuning->workgroups_per_cu) per_cu = tuning->workgroups_per_cu < (uint32_t)per_cu ? (int)tuning->workgroups_per_cu : per_cu;
@@ -308,14 +326,7 @@ int launch_batch(const DeviceState &ds, const PlanInfo &p, int which, const sf_b
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
   if (!st) hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.ws, which);
-  if (which == 0 && st)
-    hipLaunchKernelGGL(frag_batch_kernel<kSchedStatic>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
-  else if (which == 0)
-    hipLaunchKernelGGL(frag_batch_kernel<kSchedQueue>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
-  else if (st)
-    hipLaunchKernelGGL(defrag_batch_kernel<kSchedStatic>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
-  else
-    hipLaunchKernelGGL(defrag_batch_kernel<kSchedQueue>, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "batch kernel launch");
 }
@@ -339,7 +350,7 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
   if (key) aes_expand_key(key, hd->key.rk);
   uint64_t total = 0;
   uint32_t max_npriv = 1;
-  bool all_pixels = true, all_restored = true;
+  bool all_pixels = true, all_restored = true, any_mask = false;
   for (uint32_t i = 0; i < n; ++i) {
     const sf_batch_item &it = items[i];
     sf_desc d;
@@ -375,6 +386,7 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
     for (int b = 8; b < 16; ++b) lo = (lo << 8) | it.ctr0[b];
     bd.ctr_hi = hi;
     bd.ctr_lo = lo;
+    any_mask = any_mask || !compiled_mask(g.mask);
     offs[i] = (uint32_t)total;
     total += g.ntiles;
     if (total >= (1ull << 31)) return fail(SF_ERANGE, "batch holds too many tiles");
@@ -406,6 +418,7 @@ int batch_plan(const DeviceState &ds, const sf_batch_item *items, uint32_t n, co
   p.total_tiles = total;
   p.all_pixels = all_pixels;
   p.all_restored = all_restored;
+  p.any_mask = any_mask;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   for (PlanInfo &q : g_plans)
     if (q.ws == d_ws) {
