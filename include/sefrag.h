@@ -209,10 +209,10 @@ typedef struct sf_launch_shape {
   uint32_t resident;        /* 1: one resident generation of workgroups
                                (as many as the device holds at once) loops
                                over the tiles (the default of the reduced
-                               precision, and of the plain form for 8 or
-                               more private coefficients); 0: the grid gives each
-                               wavefront one tile (plain) or one pair of
-                               tiles (reduced precision)                    */
+                               precision, and of the plain form's defrag for
+                               8 or more private coefficients); 0: the grid
+                               gives each wavefront one tile (plain) or one
+                               pair of tiles (reduced precision)            */
 } sf_launch_shape;
 
 /* sf_set_launch_shape -- the shape frag_image (which = 0) or defrag_image

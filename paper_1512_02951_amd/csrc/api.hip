@@ -139,7 +139,9 @@ Shape stored_shape(DeviceState &ds, const Geom &g, int which) {
   std::lock_guard<std::mutex> lk(ds.shape_mu);
   auto it = ds.shapes.find(shape_key(g, which));
   if (it != ds.shapes.end()) return it->second;
-  return Shape{0u, g.precision == SF_FP32 && !plain_heavy(g) ? 0u : 1u};
+  // plain form: one tile per wave, except defrag of 8 or more private
+  // coefficients (resident); reduced precision: resident
+  return Shape{0u, g.precision == SF_FP32 && !(plain_heavy(g) && which == 1) ? 0u : 1u};
 }
 
 // The shape a launch of (g, which) would use, resolved (waves >= 1).

@@ -44,11 +44,13 @@ struct DefragKernelArgs {
 #define SF_FRAG_PREFETCH 0
 #endif
 
-// Each wave walks tiles t, t + stride, ...
+// Each wave walks tiles t, t + stride, ... (kLoop, the resident grids), or
+// takes the one tile t (one tile per wave: no loop and no prefetch of a next
+// tile, whose 16 pixel words would otherwise stay live through the tile).
 // kQ2Mfma: the private AC integers come from int8 matrix products (at most
 // 16 private AC coefficients); each wave then owns kQ2StageBytes of LDS
 // after its private-byte staging area.
-template <class MP, bool kQ2Mfma>
+template <class MP, bool kQ2Mfma, bool kLoop>
 __global__ __launch_bounds__(kMaxThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_kernel(FragKernelArgs a) {
   __shared__ AesLds s_aes;
   __shared__ Q2Operands s_q2[kQ2Mfma ? 64 : 1];  // B operand per lane (same for every wave)
@@ -67,6 +69,17 @@ __global__ __launch_bounds__(kMaxThreads, SF_FRAG_WAVES_PER_EU) void frag_fp32_k
   const uint32_t stride = gridDim.x * nw;
   uint32_t t = blockIdx.x * nw + wave;
   if (t >= a.g.ntiles) return;
+  if constexpr (!kLoop) {
+    const TileLane L = tile_lane(a.g, t, lane);
+    uint32_t xs[16];
+    load_block(a.g, L, xs);
+    if constexpr (kQ2Mfma)
+      frag_tile<MP, true>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K,
+                          q2stage, Q);
+    else
+      frag_tile<MP, false>(a.g, a.o, t, L, xs, lane, lp, s_aes, a.aes.enabled, a.aes.ctr_hi, a.aes.ctr_lo, a.K);
+    return;
+  }
 #if SF_FRAG_PREFETCH
   TileLane L = tile_lane(a.g, t, lane);
   uint32_t xs[16];
@@ -158,8 +171,9 @@ bool q2_on_mfma(const Geom &g) { return __builtin_popcountll(g.mask & ~1ull) <= 
 template <class MP, bool kQ2Mfma>
 int launch_frag_mp(const DeviceState &ds, const FragKernelArgs &a, const Shape &sh, hipStream_t stream) {
   const size_t lds = (size_t)sh.waves * (a.lds_priv_bytes + (kQ2Mfma ? kQ2StageBytes : 0u));
-  const int grid = grid_for(ds, (const void *)&frag_fp32_kernel<MP, kQ2Mfma>, sh, lds, a.g.ntiles);
-  hipLaunchKernelGGL((frag_fp32_kernel<MP, kQ2Mfma>), dim3(grid), dim3(64 * sh.waves), lds, stream, a);
+  void (*kern)(FragKernelArgs) = sh.resident ? frag_fp32_kernel<MP, kQ2Mfma, true> : frag_fp32_kernel<MP, kQ2Mfma, false>;
+  const int grid = grid_for(ds, (const void *)kern, sh, lds, a.g.ntiles);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * sh.waves), lds, stream, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SF_OK : hip_fail(e, "frag kernel launch");
 }
