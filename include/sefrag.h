@@ -202,10 +202,11 @@ int encrypt_private(const sf_aes_ctr *aes, uint64_t first_block, const uint8_t *
 /* One launch shape.  Host struct. */
 typedef struct sf_launch_shape {
   uint32_t waves_per_group; /* wavefronts per workgroup: 1, 2, 4, 6 or 8;
-                               0 = the form's default (plain: 4 for 8 or
-                               more private coefficients, else 2; reduced
-                               precision: the largest that lets two
-                               workgroups share a compute unit's LDS)      */
+                               0 = the form's default (plain: 4 for frag,
+                               and for defrag of 8 or more private
+                               coefficients, else 2; reduced precision: the
+                               largest that lets two workgroups share a
+                               compute unit's LDS)                          */
   uint32_t resident;        /* 1: one resident generation of workgroups
                                (as many as the device holds at once) loops
                                over the tiles (the default of the reduced

@@ -148,7 +148,7 @@ Shape stored_shape(DeviceState &ds, const Geom &g, int which) {
 static int resolved_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
   *out = in;
   if (g.precision == SF_FP32) {
-    if (!out->waves) out->waves = plain_default_waves(g);
+    if (!out->waves) out->waves = plain_default_waves(g, which);
     return plain_lds_bytes(g, which, out->waves) <= ds.max_lds_per_block
                ? SF_OK
                : fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");

@@ -190,7 +190,7 @@ int launch_defrag_mp(const DeviceState &ds, const DefragKernelArgs &a, const Sha
 // The resolved shape, or SF_ENOTSUP if its LDS does not fit a workgroup.
 int plain_shape(const DeviceState &ds, const Geom &g, int which, const Shape &in, Shape *out) {
   *out = in;
-  if (!out->waves) out->waves = plain_default_waves(g);
+  if (!out->waves) out->waves = plain_default_waves(g, which);
   if (out->waves > (uint32_t)kMaxWaves || plain_lds_bytes(g, which, out->waves) > ds.max_lds_per_block)
     return fail(SF_ENOTSUP, "launch shape: the workgroup's LDS does not fit on this device");
   return SF_OK;

@@ -110,7 +110,10 @@ uint32_t lp_default_waves(const DeviceState &ds, const Geom &g, int which);
 // for the lighter ones (measured on the 4096^2 RGB DC + 5 AC and the 8192^2
 // DC + 9 AC workloads).
 inline bool plain_heavy(const Geom &g) { return g.npriv >= 8; }
-inline uint32_t plain_default_waves(const Geom &g) { return plain_heavy(g) ? 4u : 2u; }
+// Default waves per workgroup of the plain kernels: frag 4 (one tile each,
+// up to 5 resident per SIMD by registers and LDS), defrag 4 from 8 private
+// coefficients on, else 2.
+inline uint32_t plain_default_waves(const Geom &g, int which) { return which == 0 || plain_heavy(g) ? 4u : 2u; }
 
 // Launchers (plain.hip, aes.hip).
 int launch_frag_fp32(const DeviceState &ds, const Geom &g, const uint8_t *pix, float *pub, uint8_t *priv,

@@ -53,8 +53,9 @@ CASES = [
 
 
 def test_default_shapes():
-    """The documented defaults: plain 2 waves with one tile each below 8 private
-    coefficients, 4 waves from 8 on (frag one tile each, defrag resident);
+    """The documented defaults: plain frag 4 waves with one tile each; plain
+    defrag 2 waves with one tile each below 8 private coefficients, 4 resident
+    from 8 on;
     reduced precision resident, with the largest workgroup whose LDS lets two
     share a CU (8 waves at DC + 9 AC)."""
     big = (1, 8192, 8192)
@@ -62,7 +63,7 @@ def test_default_shapes():
         _forget(big, sf.prefix_mask(5), "fp32")
         _forget(big, sf.prefix_mask(9), "fp32")
         _forget(big, sf.prefix_mask(9), "fp16")
-        assert sf.launch_shape(big, sf.prefix_mask(5), which) == (2, 0)
+        assert sf.launch_shape(big, sf.prefix_mask(5), which) == ((4, 0) if which == "frag" else (2, 0))
         assert sf.launch_shape(big, sf.prefix_mask(9), which) == (4, 0 if which == "frag" else 1)
         assert sf.launch_shape(big, sf.prefix_mask(9), which, precision="fp16") == (8, 1)
 
